@@ -1,0 +1,187 @@
+/*
+ * pmp.h — C ABI of libpmp, batched PM+32 / PM+64 hashing on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The hash families are those of Ivanchykhin, Ignatchenko and Lemire,
+ * "Regular and almost universal hashing: an efficient implementation"
+ * (arXiv 1609.09840):
+ *   - field Z_p with p = 2^32 + 15 (PM+32) or p = 2^64 + 13 (PM+64), the
+ *     smallest primes above a word power (Sec. 5, Table "smallestprimes");
+ *   - block function f_j(s) = (b_j + sum_{i<128} a_{j,i} s_i) mod p (Eq. (1)),
+ *     keys a in (0, p - kappa) with kappa = 28 / 24, b in [0, 2^n)
+ *     (Sec. 6.1, Table "parameters");
+ *   - tree construction over blocks of m = 128 words, at most 8 levels
+ *     (Algorithm 1, Sec. 4);
+ *   - byte strings become n-bit little-endian words after appending a byte
+ *     0x01 and zero bytes up to the next word boundary (end of Sec. 4);
+ *   - output h mod 2^n (Sec. 5, after Lemma 9), then the avalanche mixer of
+ *     Sec. 7 unless PMP_NO_MIX is given.
+ *
+ * Conventions the paper leaves open (fixed here, same in every entry point):
+ *   leaves always use the level-1 keys (Algorithm 1, Fig. 1); at least one
+ *   level is applied, also to strings of less than one word; the key table is
+ *   a[8][128] (level-major) followed by b[8].
+ *
+ * Memory: "device" pointers are HIP device memory (hipMalloc or a torch CUDA
+ * tensor on ROCm); "host" pointers are ordinary host memory. The caller owns
+ * every buffer passed in. The library owns only plan workspaces.
+ *
+ * Errors: every entry point returns 0 (PMP_OK) or a negative PMP_E_* code and
+ * sets a thread-local message readable with pmp_last_error(). Hash calls are
+ * asynchronous on the given stream; problems that only the device can see
+ * (offsets out of order or past the buffer) are recorded in the plan's status
+ * word and reported by pmp_plan_status().
+ */
+#ifndef PMP_H_
+#define PMP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PMP_OK 0
+#define PMP_E_INVALID_ARG (-1) /* null pointer, negative count, bad flag     */
+#define PMP_E_KEY_RANGE (-2)   /* a key a_{j,i} outside [0, p - kappa - 1]    */
+#define PMP_E_TOO_LONG (-3)    /* a string needs more than 8 levels          */
+#define PMP_E_OFFSETS (-4)     /* offsets decrease or point past buf_bytes   */
+#define PMP_E_HIP (-5)         /* a HIP runtime call failed                  */
+#define PMP_E_NOMEM (-6)       /* workspace allocation failed                */
+#define PMP_E_INTERNAL (-7)    /* device work queue overflow or stall        */
+
+/* flags for the hash calls */
+#define PMP_NO_MIX 1u    /* output h mod 2^n without the Sec. 7 mixer        */
+#define PMP_OUT_FIELD 2u /* output the field element h itself (see below)    */
+
+/* key table geometry */
+#define PMP_LEVELS 8
+#define PMP_BLOCK 128
+#define PMP_KEYS (PMP_LEVELS * PMP_BLOCK + PMP_LEVELS) /* 1032 entries */
+
+typedef struct pmp_plan pmp_plan; /* opaque: workspace + status + tuning */
+typedef struct ihipStream_t* pmp_stream_t; /* a hipStream_t (0 = null stream) */
+
+/* ---------------------------------------------------------------------- */
+/* Key tables (Eq. (1) keys; generation is a project convention because the
+ * paper only asks for keys drawn at random).
+ *
+ * pmp_expand_keys32 / pmp_expand_keys64: fill a HOST table of PMP_KEYS
+ * entries from splitmix64 started at `seed`. Entries are drawn in storage
+ * order: a[0][0..127], ..., a[7][0..127], then b[0..7]. PM+32 takes the top
+ * 32 bits of each 64-bit draw. An `a` draw outside [1, p - kappa - 1]
+ * (PM+32: [1, 2^32 - 14]; PM+64: [1, 2^64 - 12]) is discarded and drawn
+ * again; b takes the next 8 draws as they are. Returns PMP_E_INVALID_ARG if
+ * keys_out is NULL. Upload the table to the device once and keep it there. */
+int pmp_expand_keys32(uint64_t seed, uint32_t* keys_out);
+int pmp_expand_keys64(uint64_t seed, uint64_t* keys_out);
+
+/* pmp_check_keys32 / pmp_check_keys64: check a HOST key table. Every a must
+ * lie in [0, p - kappa - 1] so that a * s < 2^(2n) for every field element s
+ * (Sec. 6.1); zero keys are accepted (they make a degenerate but well-defined
+ * function, useful for tests). Returns PMP_OK or PMP_E_KEY_RANGE. */
+int pmp_check_keys32(const uint32_t* keys);
+int pmp_check_keys64(const uint64_t* keys);
+
+/* ---------------------------------------------------------------------- */
+/* Plans. A plan owns a device workspace (work queue, tree-node scratch,
+ * counters, status word) sized for a batch. Calls that share a plan must be
+ * ordered on one stream. plan == NULL in a hash call selects a default plan
+ * private to the (current device, stream) pair, created on first use.
+ * Creating or growing a workspace allocates device memory; hash calls on a
+ * plan reserved large enough do not allocate. */
+int pmp_plan_create(int device, pmp_plan** plan_out);
+int pmp_plan_destroy(pmp_plan* plan);
+/* Size the workspace for batches whose buffers total at most max_buf_bytes
+ * bytes over at most max_count strings (both variants together). */
+int pmp_plan_reserve(pmp_plan* plan, uint64_t max_buf_bytes, int64_t max_count);
+/* Synchronize `stream`, then return and clear the device-side status of
+ * `plan` (NULL: the default plan of the current device and `stream`):
+ * PMP_OK, PMP_E_OFFSETS or PMP_E_INTERNAL. */
+int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream);
+/* Lanes per 128-word block for strings longer than one block (4, 8 or 16;
+ * 0 = the built-in default). Set by the autotuner or by hand. */
+int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block);
+
+/* ---------------------------------------------------------------------- */
+/* Hashing a batch (Algorithm 1 with Eq. (1) blocks, Sec. 4 byte padding,
+ * Sec. 5 output, Sec. 7 mixer).
+ *
+ *   d_buf      device, concatenated string bytes; no alignment required
+ *   buf_bytes  number of readable bytes at d_buf (loads never go past it)
+ *   d_offsets  device, int64[count + 1]: string i is
+ *              d_buf[d_offsets[i] .. d_offsets[i+1]); offsets must be
+ *              non-decreasing and lie in [0, buf_bytes]; empty strings are
+ *              allowed. A string whose offsets break this gets no output and
+ *              the plan's status becomes PMP_E_OFFSETS.
+ *   count      number of strings (0 is a no-op)
+ *   d_keys     device, key table of PMP_KEYS entries (layout above)
+ *   d_out      device output:
+ *                pmp_hash32: uint32[count]; with PMP_OUT_FIELD uint64[count]
+ *                  holding h < 2^32 + 15
+ *                pmp_hash64: uint64[count]; with PMP_OUT_FIELD
+ *                  uint64[2 * count], pairs (h mod 2^64, h >> 64)
+ *   flags      0, PMP_NO_MIX or PMP_OUT_FIELD
+ *   stream     HIP stream the work is queued on; the call returns at once.
+ *
+ * One persistent kernel launch processes the whole batch: strings of one
+ * block are hashed one per lane, longer strings are split into level-2
+ * nodes of up to 128 blocks taken from a device work queue, and the levels
+ * above 2 are finished by whichever wave completes a node's last child. */
+int pmp_hash32(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets,
+               int64_t count, const uint32_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream);
+int pmp_hash64(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets,
+               int64_t count, const uint64_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream);
+
+/* One batch for pmp_hash_mixed: the arguments of pmp_hash32/64 in a struct.
+ * keys points to uint32[PMP_KEYS] when wide == 0, uint64[PMP_KEYS] when
+ * wide == 1. */
+typedef struct pmp_batch {
+  const uint8_t* buf;
+  uint64_t buf_bytes;
+  const int64_t* offsets;
+  int64_t count;
+  const void* keys;
+  void* out;
+  uint32_t flags;
+  uint32_t wide; /* 0: PM+32, 1: PM+64 */
+} pmp_batch;
+
+/* Hash up to two batches (any mix of PM+32 and PM+64) in ONE kernel launch;
+ * either pointer may be NULL. Same semantics per batch as pmp_hash32/64. */
+int pmp_hash_mixed(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, pmp_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Plain GPU form, kept as a baseline: one string at a time, one launch per
+ * tree level, one thread per block of 128 words. h_offsets is a HOST copy of
+ * the offsets (the baseline needs the lengths on the host to size its
+ * launches); everything else as in pmp_hash32/64. Results are identical to
+ * pmp_hash32/64. The call queues 1 + (levels - 1) launches per string and
+ * returns; d_scratch must hold 16 * ceil((max string bytes / W + 1) / 128)
+ * bytes (W = 4 or 8). */
+int pmp_hash_plain(int wide, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* h_offsets,
+                   int64_t count, const void* d_keys, void* d_out, uint32_t flags, void* d_scratch,
+                   uint64_t scratch_bytes, pmp_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Field reduction hook for tests (Sec. 6.2 fold and the corrected
+ * Algorithm 2): for each i, reduce S = w0[i] + 2^n w1[i] + 2^(2n) w2[i]
+ * (n = 32 or 64; w2[i] <= 128 as for any block sum) to z = S mod p in
+ * [0, p), on the device. PM+32: device arrays of uint32 w0, w1, w2 and
+ * uint64 z. PM+64: uint64 w0, w1, uint32 w2, and z as uint64 pairs
+ * (lo, hi). Returns PMP_E_INVALID_ARG if some w2[i] > 128 would be
+ * needed (checked on the device: such entries yield z = all ones). */
+int pmp_debug_fold(int wide, const void* d_w0, const void* d_w1, const uint32_t* d_w2, void* d_z, int64_t n,
+                   pmp_stream_t stream);
+
+/* Message for the last error on this thread (never NULL). */
+const char* pmp_last_error(void);
+/* Library version string. */
+const char* pmp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMP_H_ */

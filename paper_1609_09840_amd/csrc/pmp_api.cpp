@@ -1,0 +1,371 @@
+// Host side of libpmp: the C ABI declared in include/pmp.h.
+//
+// Argument checking, key tables, plan workspaces (one accumulator slot per
+// 128-word block of buffer, zeroed once and kept zero by the kernel), grid
+// sizing and the launches themselves. No hash arithmetic runs on the host.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "pmp.h"
+#include "pmp_internal.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PMP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// splitmix64 (Steele, Lea and Flood 2014): golden-gamma increment, then the
+// mix64 finalizer.
+uint64_t splitmix64(uint64_t* state) {
+  uint64_t z = (*state += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// largest admissible key a: p - kappa - 1 (Sec. 6.1, Table "parameters")
+constexpr uint64_t AMAX32 = 4294967296ull - 14ull;  // 2^32 + 15 - 28 - 1
+constexpr uint64_t AMAX64 = 0xfffffffffffffff4ull;  // 2^64 + 13 - 24 - 1 = 2^64 - 12
+
+}  // namespace
+
+struct pmp_plan {
+  int device = 0;
+  int32_t* status = nullptr;  // device
+  pmp::Slot* slots = nullptr;  // device
+  uint64_t nslots = 0;
+  int g32 = 8, g64 = 8;
+  uint32_t alpha = 64;       // per-string work in byte equivalents
+  uint64_t wave_bytes = 8192;  // smallest share of work worth a wave
+  int cus = 0;
+  std::mutex mu;
+};
+
+namespace {
+
+std::mutex g_default_mu;
+std::map<std::pair<int, hipStream_t>, pmp_plan*> g_default;
+
+int plan_init(pmp_plan* p, int device) {
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != device) return fail(PMP_E_INVALID_ARG, "plan device %d is not the current device %d", device, cur);
+  p->device = device;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  p->cus = prop.multiProcessorCount;
+  e = hipMalloc(&p->status, sizeof(int32_t));
+  if (e != hipSuccess) return fail(PMP_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  e = hipMemset(p->status, 0, sizeof(int32_t));
+  if (e != hipSuccess) return hip_fail(e, "hipMemset");
+  return PMP_OK;
+}
+
+// make room for n accumulator slots (zeroed)
+int plan_slots(pmp_plan* p, uint64_t n) {
+  if (n <= p->nslots) return PMP_OK;
+  hipError_t e;
+  if (p->slots) {
+    e = hipFree(p->slots);
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    p->slots = nullptr;
+    p->nslots = 0;
+  }
+  const uint64_t want = n + n / 8 + 64;
+  e = hipMalloc(&p->slots, want * sizeof(pmp::Slot));
+  if (e != hipSuccess) return fail(PMP_E_NOMEM, "workspace of %llu slots: %s", (unsigned long long)want,
+                                   hipGetErrorString(e));
+  e = hipMemset(p->slots, 0, want * sizeof(pmp::Slot));
+  if (e != hipSuccess) return hip_fail(e, "hipMemset");
+  p->nslots = want;
+  return PMP_OK;
+}
+
+uint64_t slots_for(uint64_t buf_bytes, int wide) {
+  const uint64_t blk = wide ? 1024 : 512;  // 128 words of 8 or 4 bytes
+  return (buf_bytes + blk - 1) / blk + 2;
+}
+
+int default_plan(hipStream_t stream, pmp_plan** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  auto key = std::make_pair(dev, stream);
+  auto it = g_default.find(key);
+  if (it != g_default.end()) {
+    *out = it->second;
+    return PMP_OK;
+  }
+  pmp_plan* p = new pmp_plan();
+  int r = plan_init(p, dev);
+  if (r != PMP_OK) {
+    delete p;
+    return r;
+  }
+  g_default[key] = p;
+  *out = p;
+  return PMP_OK;
+}
+
+int check_batch(const pmp_batch* b) {
+  if (!b) return PMP_OK;
+  if (b->count < 0) return fail(PMP_E_INVALID_ARG, "count %lld is negative", (long long)b->count);
+  if (b->count == 0) return PMP_OK;
+  if (!b->buf && b->buf_bytes) return fail(PMP_E_INVALID_ARG, "buf is NULL");
+  if (!b->offsets || !b->keys || !b->out) return fail(PMP_E_INVALID_ARG, "offsets, keys and out must be non-NULL");
+  if (b->flags & ~(PMP_NO_MIX | PMP_OUT_FIELD)) return fail(PMP_E_INVALID_ARG, "unknown flag bits 0x%x", b->flags);
+  if (b->wide > 1) return fail(PMP_E_INVALID_ARG, "wide must be 0 or 1");
+  const uint64_t W = b->wide ? 8 : 4;
+  if (b->buf_bytes / W >= (1ull << 56) - 1)
+    return fail(PMP_E_TOO_LONG, "a buffer of %llu bytes may hold strings of more than 2^56 words",
+                (unsigned long long)b->buf_bytes);
+  if (b->count > (int64_t)1 << 40) return fail(PMP_E_INVALID_ARG, "count too large");
+  return PMP_OK;
+}
+
+int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStream_t stream) {
+  int r = check_batch(b0);
+  if (r) return r;
+  r = check_batch(b1);
+  if (r) return r;
+  const pmp_batch* list[2];
+  int nb = 0;
+  if (b0 && b0->count > 0) list[nb++] = b0;
+  if (b1 && b1->count > 0) list[nb++] = b1;
+  if (nb == 0) return PMP_OK;
+  if (!plan) {
+    r = default_plan(stream, &plan);
+    if (r) return r;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != plan->device) return fail(PMP_E_INVALID_ARG, "plan belongs to device %d, current is %d", plan->device, dev);
+
+  std::lock_guard<std::mutex> lk(plan->mu);
+  uint64_t need = 0, work = 0;
+  for (int k = 0; k < nb; ++k) {
+    need += slots_for(list[k]->buf_bytes, (int)list[k]->wide);
+    work += list[k]->buf_bytes + (uint64_t)plan->alpha * (uint64_t)list[k]->count;
+  }
+  r = plan_slots(plan, need);
+  if (r) return r;
+
+  pmp::KArgs a;
+  std::memset(&a, 0, sizeof a);
+  uint64_t base = 0;
+  for (int k = 0; k < nb; ++k) {
+    pmp::BatchArgs& B = a.b[k];
+    B.buf = list[k]->buf;
+    B.buf_bytes = list[k]->buf_bytes;
+    B.offsets = list[k]->offsets;
+    B.count = list[k]->count;
+    B.keys = list[k]->keys;
+    B.out = list[k]->out;
+    B.flags = list[k]->flags;
+    B.wide = list[k]->wide;
+    B.slots = plan->slots + base;
+    B.nslots = slots_for(list[k]->buf_bytes, (int)list[k]->wide);
+    base += B.nslots;
+  }
+  a.nbatch = (uint32_t)nb;
+  a.alpha = plan->alpha;
+  a.status = plan->status;
+
+  // one wave per `wave_bytes` of work, at most what the device keeps resident
+  const uint64_t max_waves = (uint64_t)plan->cus * 16;
+  uint64_t waves = (work + plan->wave_bytes - 1) / plan->wave_bytes;
+  if (waves < 1) waves = 1;
+  if (waves > max_waves) waves = max_waves;
+  a.total_waves = (uint32_t)waves;
+  const int grid = (int)((waves + 3) / 4);
+  e = pmp::launch_batch(a, grid, plan->g32, plan->g64, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  return PMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pmp_last_error(void) { return g_err.c_str(); }
+const char* pmp_version(void) { return "pmp 0.1 (gfx950)"; }
+
+int pmp_expand_keys32(uint64_t seed, uint32_t* keys_out) {
+  if (!keys_out) return fail(PMP_E_INVALID_ARG, "keys_out is NULL");
+  uint64_t s = seed;
+  for (int i = 0; i < PMP_LEVELS * PMP_BLOCK; ++i) {
+    uint64_t c;
+    do {
+      c = splitmix64(&s) >> 32;
+    } while (c < 1 || c > AMAX32);
+    keys_out[i] = (uint32_t)c;
+  }
+  for (int j = 0; j < PMP_LEVELS; ++j) keys_out[PMP_LEVELS * PMP_BLOCK + j] = (uint32_t)(splitmix64(&s) >> 32);
+  return PMP_OK;
+}
+
+int pmp_expand_keys64(uint64_t seed, uint64_t* keys_out) {
+  if (!keys_out) return fail(PMP_E_INVALID_ARG, "keys_out is NULL");
+  uint64_t s = seed;
+  for (int i = 0; i < PMP_LEVELS * PMP_BLOCK; ++i) {
+    uint64_t c;
+    do {
+      c = splitmix64(&s);
+    } while (c < 1 || c > AMAX64);
+    keys_out[i] = c;
+  }
+  for (int j = 0; j < PMP_LEVELS; ++j) keys_out[PMP_LEVELS * PMP_BLOCK + j] = splitmix64(&s);
+  return PMP_OK;
+}
+
+int pmp_check_keys32(const uint32_t* keys) {
+  if (!keys) return fail(PMP_E_INVALID_ARG, "keys is NULL");
+  for (int i = 0; i < PMP_LEVELS * PMP_BLOCK; ++i)
+    if (keys[i] > AMAX32) return fail(PMP_E_KEY_RANGE, "key a[%d][%d] = %u exceeds 2^32 - 14", i / PMP_BLOCK,
+                                      i % PMP_BLOCK, keys[i]);
+  return PMP_OK;
+}
+
+int pmp_check_keys64(const uint64_t* keys) {
+  if (!keys) return fail(PMP_E_INVALID_ARG, "keys is NULL");
+  for (int i = 0; i < PMP_LEVELS * PMP_BLOCK; ++i)
+    if (keys[i] > AMAX64)
+      return fail(PMP_E_KEY_RANGE, "key a[%d][%d] = %llu exceeds 2^64 - 12", i / PMP_BLOCK, i % PMP_BLOCK,
+                  (unsigned long long)keys[i]);
+  return PMP_OK;
+}
+
+int pmp_plan_create(int device, pmp_plan** plan_out) {
+  if (!plan_out) return fail(PMP_E_INVALID_ARG, "plan_out is NULL");
+  pmp_plan* p = new pmp_plan();
+  int r = plan_init(p, device);
+  if (r) {
+    delete p;
+    return r;
+  }
+  *plan_out = p;
+  return PMP_OK;
+}
+
+int pmp_plan_destroy(pmp_plan* plan) {
+  if (!plan) return PMP_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    for (auto it = g_default.begin(); it != g_default.end(); ++it)
+      if (it->second == plan) return fail(PMP_E_INVALID_ARG, "default plans are owned by the library");
+  }
+  if (plan->slots) (void)hipFree(plan->slots);
+  if (plan->status) (void)hipFree(plan->status);
+  delete plan;
+  return PMP_OK;
+}
+
+int pmp_plan_reserve(pmp_plan* plan, uint64_t max_buf_bytes, int64_t max_count) {
+  if (!plan || max_count < 0) return fail(PMP_E_INVALID_ARG, "bad plan or count");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  // PM+32 blocks are the smaller ones, so they bound either variant; a mixed
+  // call needs at most two batches' worth of padding slots
+  return plan_slots(plan, slots_for(max_buf_bytes, 0) + 2);
+}
+
+int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!plan) {
+    int r = default_plan(s, &plan);
+    if (r) return r;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  int32_t st = 0;
+  e = hipMemcpy(&st, plan->status, sizeof st, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  if (!st) return PMP_OK;
+  // a bad batch can leave node accumulators half filled: clear everything
+  e = hipMemset(plan->status, 0, sizeof(int32_t));
+  if (e == hipSuccess && plan->slots) e = hipMemset(plan->slots, 0, plan->nslots * sizeof(pmp::Slot));
+  if (e != hipSuccess) return hip_fail(e, "hipMemset");
+  if (st & pmp::STATUS_OFFSETS)
+    return fail(PMP_E_OFFSETS, "offsets out of order or past buf_bytes (or a string over 2^56 words)");
+  return fail(PMP_E_INTERNAL, "a tree node fell outside the workspace");
+}
+
+int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block) {
+  if (!plan) return fail(PMP_E_INVALID_ARG, "plan is NULL");
+  if (lanes_per_block == 0) lanes_per_block = 8;
+  if (!pmp::batch_tile_supported(lanes_per_block))
+    return fail(PMP_E_INVALID_ARG, "lanes per block must be 4, 8 or 16 (got %d)", lanes_per_block);
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (wide) plan->g64 = lanes_per_block;
+  else plan->g32 = lanes_per_block;
+  return PMP_OK;
+}
+
+int pmp_hash32(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets, int64_t count,
+               const uint32_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream) {
+  pmp_batch b{d_buf, buf_bytes, d_offsets, count, d_keys, d_out, flags, 0};
+  return run_batches(plan, &b, nullptr, (hipStream_t)stream);
+}
+
+int pmp_hash64(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets, int64_t count,
+               const uint64_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream) {
+  pmp_batch b{d_buf, buf_bytes, d_offsets, count, d_keys, d_out, flags, 1};
+  return run_batches(plan, &b, nullptr, (hipStream_t)stream);
+}
+
+int pmp_hash_mixed(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, pmp_stream_t stream) {
+  return run_batches(plan, b0, b1, (hipStream_t)stream);
+}
+
+int pmp_hash_plain(int wide, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* h_offsets, int64_t count,
+                   const void* d_keys, void* d_out, uint32_t flags, void* d_scratch, uint64_t scratch_bytes,
+                   pmp_stream_t stream) {
+  if (count < 0 || (count > 0 && (!h_offsets || !d_keys || !d_out || !d_scratch)))
+    return fail(PMP_E_INVALID_ARG, "bad arguments");
+  if (flags & ~(PMP_NO_MIX | PMP_OUT_FIELD)) return fail(PMP_E_INVALID_ARG, "unknown flag bits");
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t o0 = h_offsets[i], o1 = h_offsets[i + 1];
+    if (o0 < 0 || o1 < o0 || (uint64_t)o1 > buf_bytes)
+      return fail(PMP_E_OFFSETS, "string %lld: offsets [%lld, %lld) outside [0, %llu]", (long long)i, (long long)o0,
+                  (long long)o1, (unsigned long long)buf_bytes);
+    hipError_t e = pmp::launch_plain_string(wide, d_buf, buf_bytes, o0, o1 - o0, d_keys, d_out, i, flags,
+                                            (uint4*)d_scratch, scratch_bytes / 16, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "plain launch (scratch too small?)");
+  }
+  return PMP_OK;
+}
+
+int pmp_debug_fold(int wide, const void* d_w0, const void* d_w1, const uint32_t* d_w2, void* d_z, int64_t n,
+                   pmp_stream_t stream) {
+  if (n < 0 || (n > 0 && (!d_w0 || !d_w1 || !d_w2 || !d_z))) return fail(PMP_E_INVALID_ARG, "bad arguments");
+  if (n == 0) return PMP_OK;
+  hipError_t e = pmp::launch_debug_fold(wide, d_w0, d_w1, d_w2, d_z, n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "fold launch");
+  return PMP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Structures shared by the host side of libpmp and its kernels (not part of
+// the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmp {
+
+constexpr uint32_t FLAG_NO_MIX = 1u;
+constexpr uint32_t FLAG_OUT_FIELD = 2u;
+
+constexpr int32_t STATUS_OFFSETS = 1;   // an offsets pair was out of order or out of range
+constexpr int32_t STATUS_INTERNAL = 2;  // a node accumulator fell outside the workspace
+
+// Accumulator of one tree node (level >= 2): a sum of field elements
+// lo + 2^64 hi and the weight received so far. All zero between launches.
+struct Slot {
+  uint64_t lo;
+  uint32_t hi;
+  uint32_t cnt;
+};
+
+// One batch as the kernel sees it.
+struct BatchArgs {
+  const uint8_t* buf;
+  uint64_t buf_bytes;
+  const int64_t* offsets;
+  int64_t count;
+  const void* keys;  // uint32[1032] (PM+32) or uint64[1032] (PM+64)
+  void* out;
+  uint32_t flags;
+  uint32_t wide;
+  Slot* slots;  // ceil(buf_bytes / (128 W)) + 1 node accumulators
+  uint64_t nslots;
+};
+
+struct KArgs {
+  BatchArgs b[2];
+  uint32_t nbatch;
+  uint32_t alpha;        // per-string work in byte equivalents
+  int32_t* status;       // device status word (STATUS_* bits)
+  uint32_t total_waves;  // waves sharing the work (grid * 4 or fewer)
+};
+
+// kernels/launchers (pmp_kernels.hip)
+hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s);
+bool batch_tile_supported(int g);
+hipError_t launch_plain_string(int wide, const uint8_t* buf, uint64_t buf_bytes, int64_t o0, int64_t len,
+                               const void* keys, void* out, int64_t index, uint32_t flags, uint4* scratch,
+                               uint64_t scratch_slots, hipStream_t s);
+hipError_t launch_debug_fold(int wide, const void* w0, const void* w1, const uint32_t* w2, void* z, int64_t n,
+                             hipStream_t s);
+
+}  // namespace pmp

@@ -1,0 +1,262 @@
+"""Python binding of libpmp (ctypes): the C ABI of include/pmp.h with the same
+names. It only marshals arguments; every hash step runs in the library's HIP
+kernels. PyTorch supplies device memory and streams.
+
+The library must be built (``python -m paper_1609_09840_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+PMP_OK = 0
+PMP_E_INVALID_ARG = -1
+PMP_E_KEY_RANGE = -2
+PMP_E_TOO_LONG = -3
+PMP_E_OFFSETS = -4
+PMP_E_HIP = -5
+PMP_E_NOMEM = -6
+PMP_E_INTERNAL = -7
+
+PMP_NO_MIX = 1
+PMP_OUT_FIELD = 2
+PMP_KEYS = 1032
+
+
+class PmpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pmp error {code}: {msg}")
+        self.code = code
+
+
+class pmp_batch(ctypes.Structure):
+    _fields_ = [
+        ("buf", ctypes.c_void_p),
+        ("buf_bytes", ctypes.c_uint64),
+        ("offsets", ctypes.c_void_p),
+        ("count", ctypes.c_int64),
+        ("keys", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+        ("wide", ctypes.c_uint32),
+    ]
+
+
+def _load():
+    if not os.path.exists(_build.LIB):
+        raise ImportError(f"libpmp.so is not built ({_build.LIB}); run __graft_entry__.build()")
+    # Load PyTorch's HIP runtime first so that libpmp.so binds to the same
+    # runtime instance (one per process) instead of a second copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(_build.LIB)
+    vp, u64, i64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int
+    sig = {
+        "pmp_expand_keys32": [u64, vp],
+        "pmp_expand_keys64": [u64, vp],
+        "pmp_check_keys32": [vp],
+        "pmp_check_keys64": [vp],
+        "pmp_plan_create": [i32, ctypes.POINTER(vp)],
+        "pmp_plan_destroy": [vp],
+        "pmp_plan_reserve": [vp, u64, i64],
+        "pmp_plan_status": [vp, vp],
+        "pmp_plan_set_tile": [vp, i32, i32],
+        "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
+        "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
+        "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
+        "pmp_hash_plain": [i32, vp, u64, vp, i64, vp, vp, u32, vp, u64, vp],
+        "pmp_debug_fold": [i32, vp, vp, vp, vp, i64, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.pmp_last_error.restype = ctypes.c_char_p
+    lib.pmp_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+LIB_PATH = _build.LIB
+
+
+def _check(rc: int) -> int:
+    if rc != PMP_OK:
+        raise PmpError(rc, _lib.pmp_last_error().decode())
+    return rc
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev_ptr(t, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def pmp_version() -> str:
+    return _lib.pmp_version().decode()
+
+
+def pmp_last_error() -> str:
+    return _lib.pmp_last_error().decode()
+
+
+# -- keys ------------------------------------------------------------------
+def pmp_expand_keys32(seed: int) -> np.ndarray:
+    k = np.zeros(PMP_KEYS, dtype=np.uint32)
+    _check(_lib.pmp_expand_keys32(seed, k.ctypes.data_as(ctypes.c_void_p)))
+    return k
+
+
+def pmp_expand_keys64(seed: int) -> np.ndarray:
+    k = np.zeros(PMP_KEYS, dtype=np.uint64)
+    _check(_lib.pmp_expand_keys64(seed, k.ctypes.data_as(ctypes.c_void_p)))
+    return k
+
+
+def pmp_check_keys32(keys: np.ndarray) -> int:
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    return _lib.pmp_check_keys32(k.ctypes.data_as(ctypes.c_void_p))
+
+
+def pmp_check_keys64(keys: np.ndarray) -> int:
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    return _lib.pmp_check_keys64(k.ctypes.data_as(ctypes.c_void_p))
+
+
+# -- plans -----------------------------------------------------------------
+class Plan:
+    """Owned plan (workspace + status word) on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.pmp_plan_create(device, ctypes.byref(h)))
+        self.handle = h
+
+    def reserve(self, max_buf_bytes: int, max_count: int):
+        _check(_lib.pmp_plan_reserve(self.handle, max_buf_bytes, max_count))
+
+    def set_tile(self, wide: bool, lanes_per_block: int):
+        _check(_lib.pmp_plan_set_tile(self.handle, int(wide), lanes_per_block))
+
+    def status(self, stream=None) -> int:
+        return _lib.pmp_plan_status(self.handle, _stream(stream))
+
+    def close(self):
+        if self.handle:
+            _check(_lib.pmp_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pmp_plan_create(device: int = 0) -> Plan:
+    return Plan(device)
+
+
+def pmp_plan_status(plan: Plan | None = None, stream=None) -> int:
+    return _lib.pmp_plan_status(plan.handle if plan else None, _stream(stream))
+
+
+def _plan_ptr(plan):
+    return plan.handle if plan is not None else None
+
+
+# -- hashing ---------------------------------------------------------------
+def _out_for(wide: bool, count: int, flags: int, device):
+    import torch
+
+    if flags & PMP_OUT_FIELD:
+        return torch.empty(count * (2 if wide else 1), dtype=torch.uint64, device=device)
+    return torch.empty(count, dtype=torch.uint64 if wide else torch.uint32, device=device)
+
+
+def _hash(wide, buf, offsets, keys, out, flags, stream, plan, buf_bytes):
+    import torch
+
+    count = offsets.numel() - 1
+    if out is None:
+        out = _out_for(wide, count, flags, offsets.device)
+    if buf_bytes is None:
+        buf_bytes = buf.numel()
+    if keys.dtype != (torch.uint64 if wide else torch.uint32) or keys.numel() != PMP_KEYS:
+        raise ValueError("keys must be a device tensor of 1032 uint32 (PM+32) or uint64 (PM+64)")
+    if offsets.dtype != torch.int64:
+        raise ValueError("offsets must be int64")
+    f = _lib.pmp_hash64 if wide else _lib.pmp_hash32
+    bp = _dev_ptr(buf, "buf") if buf.numel() else ctypes.c_void_p(0)
+    _check(f(_plan_ptr(plan), bp, buf_bytes, _dev_ptr(offsets, "offsets"), count, _dev_ptr(keys, "keys"),
+             _dev_ptr(out, "out"), flags, _stream(stream)))
+    return out
+
+
+def pmp_hash32(buf, offsets, keys, out=None, flags: int = 0, stream=None, plan: Plan | None = None,
+               buf_bytes: int | None = None):
+    """PM+32 of string i = buf[offsets[i]:offsets[i+1]] for every i (device
+    tensors: uint8 buf, int64 offsets, uint32[1032] keys). Returns out."""
+    return _hash(False, buf, offsets, keys, out, flags, stream, plan, buf_bytes)
+
+
+def pmp_hash64(buf, offsets, keys, out=None, flags: int = 0, stream=None, plan: Plan | None = None,
+               buf_bytes: int | None = None):
+    """PM+64 counterpart of pmp_hash32 (uint64[1032] keys)."""
+    return _hash(True, buf, offsets, keys, out, flags, stream, plan, buf_bytes)
+
+
+def make_batch(wide: bool, buf, offsets, keys, out, flags: int = 0, buf_bytes: int | None = None) -> pmp_batch:
+    return pmp_batch(
+        buf=(buf.data_ptr() if buf.numel() else 0),
+        buf_bytes=buf.numel() if buf_bytes is None else buf_bytes,
+        offsets=offsets.data_ptr(),
+        count=offsets.numel() - 1,
+        keys=keys.data_ptr(),
+        out=out.data_ptr(),
+        flags=flags,
+        wide=1 if wide else 0,
+    )
+
+
+def pmp_hash_mixed(b0: pmp_batch | None, b1: pmp_batch | None, stream=None, plan: Plan | None = None):
+    """Both batches in one kernel launch (see make_batch)."""
+    p0 = ctypes.byref(b0) if b0 is not None else None
+    p1 = ctypes.byref(b1) if b1 is not None else None
+    _check(_lib.pmp_hash_mixed(_plan_ptr(plan), p0, p1, _stream(stream)))
+
+
+def pmp_hash_plain(wide: bool, buf, h_offsets: np.ndarray, keys, out, flags: int, scratch, stream=None):
+    """Baseline: one string per launch sequence (host offsets)."""
+    h = np.ascontiguousarray(h_offsets, dtype=np.int64)
+    _check(_lib.pmp_hash_plain(int(wide), _dev_ptr(buf, "buf"), buf.numel(), h.ctypes.data_as(ctypes.c_void_p),
+                               len(h) - 1, _dev_ptr(keys, "keys"), _dev_ptr(out, "out"), flags,
+                               _dev_ptr(scratch, "scratch"), scratch.numel() * scratch.element_size(),
+                               _stream(stream)))
+    return out
+
+
+def pmp_debug_fold(wide: bool, w0, w1, w2, z, stream=None):
+    n = w2.numel()
+    _check(_lib.pmp_debug_fold(int(wide), _dev_ptr(w0, "w0"), _dev_ptr(w1, "w1"), _dev_ptr(w2, "w2"),
+                               _dev_ptr(z, "z"), n, _stream(stream)))
+    return z

@@ -1,0 +1,66 @@
+"""Helpers shared by the GPU tests: move a Ragged batch to the device, run the
+library, run the oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+MODES = {0: oracle.MIXED, 1: oracle.RAW, 2: oracle.FIELD}  # library flags -> oracle modes
+
+
+def dev():
+    import torch
+
+    return torch.device("cuda:0")
+
+
+def keys_for(wide: bool, seed: int):
+    from paper_1609_09840_amd import pmp
+
+    return pmp.pmp_expand_keys64(seed) if wide else pmp.pmp_expand_keys32(seed)
+
+
+def to_dev_keys(keys_np: np.ndarray):
+    import torch
+
+    wide = keys_np.dtype == np.uint64
+    t = torch.from_numpy(keys_np.view(np.int64) if wide else keys_np.view(np.int32)).to(dev())
+    return t.view(torch.uint64 if wide else torch.uint32)
+
+
+def to_dev(rg):
+    import torch
+
+    buf = torch.from_numpy(rg.buf if rg.buf.size else np.zeros(1, np.uint8)).to(dev())
+    if not rg.buf.size:
+        buf = buf[:0]
+    off = torch.from_numpy(rg.offsets).to(dev())
+    return buf, off
+
+
+def gpu_hash(rg, keys_np, flags=0, plan=None, buf=None, off=None):
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    if buf is None:
+        buf, off = to_dev(rg)
+    keys = to_dev_keys(keys_np)
+    f = pmp.pmp_hash64 if rg.wide else pmp.pmp_hash32
+    out = f(buf, off, keys, flags=flags, plan=plan)
+    torch.cuda.synchronize()
+    return as_u64(out.cpu().numpy())
+
+
+def as_u64(a: np.ndarray) -> np.ndarray:
+    return a.reshape(-1).astype(np.uint64)
+
+
+def oracle_hash(rg, keys_np, flags=0, nthreads=8):
+    return as_u64(oracle.load().batch(rg.wide, rg.buf, rg.offsets, keys_np, MODES[flags], nthreads=nthreads))
+
+
+def first_mismatch(got, want):
+    bad = np.nonzero(got != want)[0]
+    return None if bad.size == 0 else (int(bad[0]), int(got[bad[0]]), int(want[bad[0]]), int(bad.size))

@@ -1,0 +1,286 @@
+"""GPU path vs the CPU oracle, bit for bit, through the C ABI.
+
+Every case prints what it runs before touching the GPU. Inputs are the
+seeded generators of paper_1609_09840_amd.workloads; expected values come
+from the oracle only."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gpu_util as U
+from paper_1609_09840_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def check(rg, keys_np, flags=0, label=""):
+    say(f"case {label}: wide={rg.wide} count={rg.count} bytes={rg.nbytes} flags={flags}")
+    got = U.gpu_hash(rg, keys_np, flags)
+    want = U.oracle_hash(rg, keys_np, flags)
+    assert got.shape == want.shape
+    assert U.first_mismatch(got, want) is None, (label, U.first_mismatch(got, want))
+
+
+def edge_lengths(wide):
+    Wb = 8 if wide else 4
+    blk = 128 * Wb
+    ls = list(range(0, 3 * Wb + 2))
+    for base in (blk, 2 * blk, 64 * blk, 127 * blk, 128 * blk, 129 * blk, 128 * 128 * blk // 128 * 2):
+        ls += [base - Wb - 1, base - Wb, base - 1, base, base + 1, base + Wb]
+    return [x for x in ls if x >= 0]
+
+
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("lead", [0, 1, 2, 3])
+def test_edge_lengths(wide, lead):
+    """Word, block and node boundaries, every start alignment."""
+    rg = W.from_lengths(edge_lengths(wide), 300 + lead, wide, lead=lead)
+    check(rg, U.keys_for(wide, 11), 0, f"edges lead={lead}")
+
+
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_output_modes(wide, flags):
+    rng = np.random.default_rng(21)
+    lengths = np.concatenate([[0, 1, 7, 8, 9], rng.integers(0, 5000, size=500)])
+    rg = W.from_lengths(lengths, 22, wide, lead=5)
+    check(rg, U.keys_for(wide, 23), flags, "modes")
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_three_and_four_levels(wide):
+    """Strings that need 3 and 4 tree levels, cut at node boundaries."""
+    Wb = 8 if wide else 4
+    node = 128 * 128 * Wb  # bytes of one level-2 node
+    lengths = [node - Wb, node, node + 1, 3 * node + 17, 128 * node - Wb, 128 * node, 128 * node + 5]
+    rg = W.from_lengths(lengths, 31, wide, lead=3)
+    check(rg, U.keys_for(wide, 32), 2, "levels")
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_max_keys_max_data(wide):
+    """Largest admissible keys and all-0xff data: the largest block sums."""
+    from paper_1609_09840_amd import pmp
+
+    keys = U.keys_for(wide, 1)
+    amax = (1 << 64) - 12 if wide else (1 << 32) - 14
+    keys[:1024] = amax
+    keys[1024:] = (1 << 64) - 1 if wide else (1 << 32) - 1
+    assert (pmp.pmp_check_keys64 if wide else pmp.pmp_check_keys32)(keys) == 0
+    lengths = [0, 1, 500, 1016, 1024, 5000, 70000, 300000]
+    rg = W.from_lengths(lengths, 41, wide)
+    rg.buf[:] = 0xFF
+    for flags in (0, 2):
+        check(rg, keys, flags, "max")
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_zero_keys(wide):
+    """All-zero keys (accepted) give b_1 for one block and the tree of b's."""
+    keys = np.zeros(1032, dtype=np.uint64 if wide else np.uint32)
+    keys[1024:] = np.arange(1, 9)
+    rg = W.from_lengths([0, 5, 600, 2000, 200000], 42, wide)
+    check(rg, keys, 2, "zero keys")
+
+
+def test_c1_full():
+    wl = W.c1()
+    check(wl.batches[0], U.keys_for(False, W.KEY_SEED32), 0, "c1")
+
+
+def test_c2_slice():
+    wl = W.c2(count=1 << 14)
+    check(wl.batches[0], U.keys_for(False, W.KEY_SEED32), 0, "c2 2^14")
+
+
+def test_c3_small():
+    wl = W.c3(count=3, length=(16 << 20) // 8 + 1000)
+    check(wl.batches[0], U.keys_for(True, W.KEY_SEED64), 0, "c3 small")
+
+
+def test_c4_slice_mixed_launch():
+    """Both variants in ONE launch (pmp_hash_mixed) vs the oracle."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    wl = W.c4(count=1 << 13)
+    outs, wants = [], []
+    batches = []
+    keep = []
+    for rg in wl.batches:
+        kn = U.keys_for(rg.wide, W.KEY_SEED64 if rg.wide else W.KEY_SEED32)
+        buf, off = U.to_dev(rg)
+        keys = U.to_dev_keys(kn)
+        out = torch.empty(rg.count, dtype=torch.uint64 if rg.wide else torch.uint32, device=U.dev())
+        keep += [buf, off, keys, out]
+        batches.append(pmp.make_batch(rg.wide, buf, off, keys, out))
+        outs.append(out)
+        wants.append(U.oracle_hash(rg, kn))
+    say(f"case c4 mixed: {wl.count} strings, {wl.nbytes} bytes")
+    pmp.pmp_hash_mixed(batches[0], batches[1])
+    torch.cuda.synchronize()
+    for out, want in zip(outs, wants):
+        got = U.as_u64(out.cpu().numpy())
+        assert U.first_mismatch(got, want) is None, U.first_mismatch(got, want)
+    assert pmp.pmp_plan_status() == 0
+
+
+def test_alone_equals_in_batch():
+    """A string hashes the same alone as inside any batch (batch invariance)."""
+    rng = np.random.default_rng(51)
+    for wide in (False, True):
+        lengths = rng.integers(0, 200000, size=40)
+        rg = W.from_lengths(lengths, 52, wide, lead=2)
+        keys = U.keys_for(wide, 53)
+        full = U.gpu_hash(rg, keys, 2)
+        for i in (0, 7, 39):
+            one = W.Ragged(rg.buf, rg.offsets[i:i + 2].copy(), wide)
+            got = U.gpu_hash(one, keys, 2)
+            stride = 2 if wide else 1
+            assert np.array_equal(got, full[stride * i:stride * (i + 1)])
+
+
+def test_empty_and_zero_count():
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rg = W.from_lengths([0, 0, 0], 61, False)
+    check(rg, U.keys_for(False, 62), 0, "empties")
+    buf = torch.zeros(4, dtype=torch.uint8, device=U.dev())
+    off = torch.zeros(1, dtype=torch.int64, device=U.dev())
+    keys = U.to_dev_keys(U.keys_for(False, 62))
+    out = pmp.pmp_hash32(buf, off, keys)
+    torch.cuda.synchronize()
+    assert out.numel() == 0
+
+
+def test_misaligned_buffer_pointer():
+    """The buffer pointer itself unaligned (a view one byte in)."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    for wide in (False, True):
+        rg = W.from_lengths([5, 100, 1000, 70000, 3], 71, wide)
+        raw = torch.from_numpy(np.concatenate([[0xAB], rg.buf, [0xCD]]).astype(np.uint8)).to(U.dev())
+        buf = raw[1:1 + rg.buf.size]
+        off = torch.from_numpy(rg.offsets).to(U.dev())
+        keys_np = U.keys_for(wide, 72)
+        out = (pmp.pmp_hash64 if wide else pmp.pmp_hash32)(buf, off, U.to_dev_keys(keys_np), flags=2,
+                                                           buf_bytes=rg.buf.size)
+        torch.cuda.synchronize()
+        got = U.as_u64(out.cpu().numpy())
+        assert U.first_mismatch(got, U.oracle_hash(rg, keys_np, 2)) is None
+
+
+def test_bad_offsets_reported():
+    """Decreasing offsets: status PMP_E_OFFSETS, the good strings still hash."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    plan = pmp.Plan(0)
+    rg = W.from_lengths([10, 20, 30, 40], 81, False)
+    offs = rg.offsets.copy()
+    offs[2] = offs[1] - 5  # string 1 runs backwards
+    buf = torch.from_numpy(rg.buf).to(U.dev())
+    off = torch.from_numpy(offs).to(U.dev())
+    keys_np = U.keys_for(False, 82)
+    out = pmp.pmp_hash32(buf, off, U.to_dev_keys(keys_np), flags=2, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == pmp.PMP_E_OFFSETS
+    assert plan.status() == pmp.PMP_OK  # cleared
+    got = U.as_u64(out.cpu().numpy())
+    want = U.oracle_hash(W.Ragged(rg.buf, np.array([offs[0], offs[1]]), False), keys_np, 2)
+    assert got[0] == want[0]
+    plan.close()
+
+
+def test_tiles_agree():
+    """Every lanes-per-block setting gives the same results."""
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(91)
+    for wide in (False, True):
+        rg = W.from_lengths(rng.integers(0, 300000, size=30), 92, wide, lead=1)
+        keys = U.keys_for(wide, 93)
+        want = U.oracle_hash(rg, keys, 2)
+        for g in (4, 8, 16):
+            plan = pmp.Plan(0)
+            plan.set_tile(wide, g)
+            say(f"case tile G={g} wide={wide}")
+            got = U.gpu_hash(rg, keys, 2, plan=plan)
+            assert U.first_mismatch(got, want) is None, (g, U.first_mismatch(got, want))
+            plan.close()
+
+
+def test_plain_form_matches():
+    """The one-string-per-launch baseline gives identical results."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(95)
+    for wide in (False, True):
+        rg = W.from_lengths(np.concatenate([[0, 1, 511, 512, 1024], rng.integers(0, 100000, size=20)]), 96, wide)
+        keys_np = U.keys_for(wide, 97)
+        buf, _ = U.to_dev(rg)
+        keys = U.to_dev_keys(keys_np)
+        for flags in (0, 2):
+            out = torch.empty(rg.count * (2 if (wide and flags == 2) else 1),
+                              dtype=torch.uint64 if (wide or flags == 2) else torch.uint32, device=U.dev())
+            scratch = torch.empty(1 << 20, dtype=torch.uint8, device=U.dev())
+            pmp.pmp_hash_plain(wide, buf, rg.offsets, keys, out, flags, scratch)
+            torch.cuda.synchronize()
+            got = U.as_u64(out.cpu().numpy())
+            assert U.first_mismatch(got, U.oracle_hash(rg, keys_np, flags)) is None
+
+
+# --- field reduction (Sec. 6.2 fold + Algorithm 2) vs exact integers --------
+def _fold_cases(n, k, rng, count):
+    M = (1 << n) - 1
+    w0s = [0, 1, k - 1, k, 2 * k - 1, 2 * k, M - k * k, M - 2 * k, M - k, M - 1, M]
+    w1s = [0, 1, 2, M // k, M // k + 1, M - 1, M]
+    w2s = [0, 1, 2, 64, 127, 128]
+    cases = [(a, b, c) for a in w0s for b in w1s for c in w2s]
+    # sums S = b + sum a_i s_i of max keys and max data
+    amax = (1 << n) - k + 1
+    for t in range(1, 129):
+        S = (1 << n) - 1 + t * amax * M
+        cases.append((S & M, (S >> n) & M, S >> (2 * n)))
+    for _ in range(count):
+        S = int.from_bytes(rng.bytes(2 * n // 8 + 1), "little") % (129 << (2 * n))
+        cases.append((S & M, (S >> n) & M, S >> (2 * n)))
+    return cases
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_fold_matches_exact_mod(wide):
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    n, k = (64, 13) if wide else (32, 15)
+    p = (1 << n) + k
+    rng = np.random.default_rng(7)
+    cases = _fold_cases(n, k, rng, 100000)
+    say(f"case fold wide={wide}: {len(cases)} sums")
+    w0 = np.array([c[0] for c in cases], dtype=np.uint64 if wide else np.uint32)
+    w1 = np.array([c[1] for c in cases], dtype=np.uint64 if wide else np.uint32)
+    w2 = np.array([c[2] for c in cases], dtype=np.uint32)
+    tdev = lambda a: torch.from_numpy(a.view(np.int64) if a.dtype == np.uint64 else a.view(np.int32)).to(U.dev())
+    z = torch.zeros(len(cases) * (2 if wide else 1), dtype=torch.int64, device=U.dev())
+    pmp.pmp_debug_fold(wide, tdev(w0), tdev(w1), tdev(w2), z)
+    torch.cuda.synchronize()
+    zz = z.cpu().numpy().view(np.uint64)
+    for idx, (a, b, c) in enumerate(cases):
+        S = a + (b << n) + (c << (2 * n))
+        got = (int(zz[2 * idx]) + (int(zz[2 * idx + 1]) << 64)) if wide else int(zz[idx])
+        assert got == S % p, (a, b, c, got, S % p)
