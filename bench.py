@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Benchmark: GB/s hashed by the batched PM+32/PM+64 path on one MI355X.
+
+A step is one pmp_hash_mixed call (one kernel launch) over a whole batch whose
+inputs already sit in HBM. The default workload is the ragged mixed batch:
+2^18 strings, lengths round(LogNormal(ln 200, 2.0)) clamped to [1 B, 1 MiB],
+each string PM+32 or PM+64 with probability 1/2. Other workloads: --config
+c1 | c2 | c3 (see paper_1609_09840_amd/workloads.py).
+
+Prints ONE JSON line. Besides the headline value it carries:
+  roofline      algorithmic bytes per launch / mean launch time (HIP events
+                on the launch stream) against the 8 TB/s HBM peak; `traffic`
+                is the measured HBM bytes per launch from the committed
+                rocprofv3 counter summary when it was taken on the current
+                kernel source, else null;
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload;
+  plain_gpu     the one-string-per-launch GPU form on a prefix of the batch.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GB/s hashed (PM+32/64, ragged batch) vs roofline & plain GPU; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL = "batch_kernel"
+DESCR = {
+    "c1": "PM+32, 1024 strings x 64 B",
+    "c2": "PM+32, 2^20 strings, lengths uniform in [8, 256] B",
+    "c3": "PM+64, 64 strings x 16 MiB",
+    "c4": "2^18 strings, lengths round(LogNormal(ln 200, 2.0)) clamped to [1 B, 1 MiB], "
+          "half PM+32 / half PM+64, one launch",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("pmp_kernels.hip", "pmp_device.hpp", "pmp_internal.h"):
+        with open(os.path.join(ROOT, "paper_1609_09840_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(config: str):
+    """HBM bytes per launch from profiles/<kernel>_<config>_counters.json if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{config}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def algorithmic_bytes(wl) -> int:
+    """payload + offsets + outputs + key tables: every byte the path must
+    move at least once."""
+    tot = 0
+    for rg in wl.batches:
+        tot += rg.nbytes + 8 * (rg.count + 1) + (8 if rg.wide else 4) * rg.count + 1032 * (8 if rg.wide else 4)
+    return tot
+
+
+def setup(wl, dev):
+    import torch
+
+    from paper_1609_09840_amd import pmp
+    from paper_1609_09840_amd import workloads as W
+
+    keep, batches = [], []
+    for rg in wl.batches:
+        kn = pmp.pmp_expand_keys64(W.KEY_SEED64) if rg.wide else pmp.pmp_expand_keys32(W.KEY_SEED32)
+        buf = torch.from_numpy(rg.buf).to(dev)
+        off = torch.from_numpy(rg.offsets).to(dev)
+        keys = torch.from_numpy(kn.view(np.int64) if rg.wide else kn.view(np.int32)).to(dev)
+        keys = keys.view(torch.uint64 if rg.wide else torch.uint32)
+        out = torch.empty(rg.count, dtype=torch.uint64 if rg.wide else torch.uint32, device=dev)
+        keep.append((rg, kn, buf, off, keys, out))
+        batches.append(pmp.make_batch(rg.wide, buf, off, keys, out))
+    while len(batches) < 2:
+        batches.append(None)
+    return keep, batches
+
+
+def cpu_baseline(wl, target_cpu_s: float = 12.0):
+    """The oracle as it stands, on a prefix of each batch sized for about
+    `target_cpu_s` CPU-seconds, all host threads."""
+    import oracle
+    from paper_1609_09840_amd import pmp
+    from paper_1609_09840_amd import workloads as W
+
+    orc = oracle.load()
+    threads = min(os.cpu_count() or 1, 64)
+    # measure the oracle's per-thread speed on a small prefix first
+    probe_bytes, probe_s = 0, 0.0
+    for rg in wl.batches:
+        kn = pmp.pmp_expand_keys64(W.KEY_SEED64) if rg.wide else pmp.pmp_expand_keys32(W.KEY_SEED32)
+        n = int(np.searchsorted(rg.offsets, rg.offsets[0] + (4 << 20)))
+        n = max(1, min(n, rg.count))
+        t0 = time.perf_counter()
+        orc.batch(rg.wide, rg.buf, rg.offsets[: n + 1], kn, oracle.MIXED, nthreads=1)
+        probe_s += time.perf_counter() - t0
+        probe_bytes += int(rg.offsets[n] - rg.offsets[0])
+    per_thread = probe_bytes / max(probe_s, 1e-9)
+    budget = per_thread * target_cpu_s  # bytes for ~target_cpu_s CPU-seconds
+    share = budget / max(wl.nbytes, 1)
+    tot_bytes, tot_s, nstr = 0, 0.0, 0
+    for rg in wl.batches:
+        kn = pmp.pmp_expand_keys64(W.KEY_SEED64) if rg.wide else pmp.pmp_expand_keys32(W.KEY_SEED32)
+        want = rg.offsets[0] + int(share * rg.nbytes)
+        n = int(np.searchsorted(rg.offsets, want))
+        n = max(1, min(n, rg.count))
+        t0 = time.perf_counter()
+        orc.batch(rg.wide, rg.buf, rg.offsets[: n + 1], kn, oracle.MIXED, nthreads=threads)
+        tot_s += time.perf_counter() - t0
+        tot_bytes += int(rg.offsets[n] - rg.offsets[0])
+        nstr += n
+    return {
+        "value": round(tot_bytes / tot_s / 1e9, 4),
+        "unit": "GB/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {nstr} strings ({tot_bytes} bytes, {100.0 * tot_bytes / wl.nbytes:.1f}% of the payload, "
+                  f"both variants in proportion), {tot_s:.2f} s wall on {threads} threads",
+    }
+
+
+def plain_gpu(keep, dev, max_strings: int = 4000):
+    """The one-string-per-launch GPU form on a prefix of each batch."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    tot_bytes, tot_s, nstr = 0, 0.0, 0
+    share = max_strings / sum(k[0].count for k in keep)
+    for rg, kn, buf, off, keys, out in keep:
+        n = max(1, int(rg.count * share))
+        h = rg.offsets[: n + 1]
+        o = torch.empty(n, dtype=out.dtype, device=dev)
+        pmp.pmp_hash_plain(rg.wide, buf, h, keys, o, 0, scratch)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pmp.pmp_hash_plain(rg.wide, buf, h, keys, o, 0, scratch)
+        torch.cuda.synchronize()
+        tot_s += time.perf_counter() - t0
+        tot_bytes += int(h[-1] - h[0])
+        nstr += n
+        if not torch.equal(o, out[:n]):
+            raise RuntimeError("plain GPU form disagrees with the batched path")
+    return {"value": round(tot_bytes / tot_s / 1e9, 4), "unit": "GB/s",
+            "sample": f"first {nstr} strings of the batch ({tot_bytes} bytes), same outputs as the batched path"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c4", choices=sorted(DESCR))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain GPU form")
+    ap.add_argument("--g32", type=int, default=0, help="lanes per block, PM+32 (0: default)")
+    ap.add_argument("--g64", type=int, default=0, help="lanes per block, PM+64 (0: default)")
+    ap.add_argument("--waves-per-cu", type=int, default=0, help="waves per CU (0: as many as stay resident)")
+    ap.add_argument("--alpha", type=int, default=0, help="per-string work weight in bytes (0: default)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1609_09840_amd import pmp
+    from paper_1609_09840_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.CONFIGS[args.config]()
+    keep, batches = setup(wl, dev)
+    plan = pmp.Plan(0)
+    if args.g32:
+        plan.set_tile(False, args.g32)
+    if args.g64:
+        plan.set_tile(True, args.g64)
+    plan.tune(args.waves_per_cu, args.alpha, 0)
+    plan.reserve(sum(rg.buf.size for rg in wl.batches), wl.count)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        pmp.pmp_hash_mixed(batches[0], batches[1], stream=stream, plan=plan)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if plan.status() != pmp.PMP_OK:
+        raise RuntimeError("device status not OK after warmup")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    if plan.status() != pmp.PMP_OK:
+        raise RuntimeError("device status not OK after the timed steps")
+
+    payload = wl.nbytes
+    value = payload * args.steps / wall / 1e9
+    alg = algorithmic_bytes(wl)
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    traffic = read_traffic(args.config)
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded PCG64 bytes and lengths)",
+        "config": {
+            "workload": f"{args.config}: {DESCR[args.config]}",
+            "strings": wl.count,
+            "payload_bytes": payload,
+            "lanes_per_block": {"pm32": plan_g(args.g32), "pm64": plan_g(args.g64, True)},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": KERNEL,
+            "algorithmic_bytes_per_launch": alg,
+            "mean_launch_ms": round(launch_ms, 5),
+        },
+    }
+    if not args.no_plain:
+        rec["plain_gpu"] = plain_gpu(keep, dev)
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(rec), flush=True)
+
+
+def plan_g(g: int, wide: bool = False) -> int:
+    return g if g else (16 if wide else 8)
+
+
+if __name__ == "__main__":
+    main()

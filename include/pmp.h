@@ -101,9 +101,15 @@ int pmp_plan_reserve(pmp_plan* plan, uint64_t max_buf_bytes, int64_t max_count);
  * `plan` (NULL: the default plan of the current device and `stream`):
  * PMP_OK, PMP_E_OFFSETS or PMP_E_INTERNAL. */
 int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream);
-/* Lanes per 128-word block for strings longer than one block (4, 8 or 16;
- * 0 = the built-in default). Set by the autotuner or by hand. */
+/* Lanes per 128-word block for strings longer than one block, per variant
+ * (wide = 0: PM+32, 1: PM+64; 0 = the default, 8 and 16). Compiled pairs:
+ * (8,16) (8,8) (16,16) (4,16) (16,8) (4,8); others give PMP_E_INVALID_ARG.
+ * Set by the autotuner or by hand. */
 int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block);
+/* Launch shape: waves per CU (0 = as many as stay resident), the per-string
+ * work weight alpha in byte equivalents used to split a batch between waves
+ * (0 = keep), and the smallest share of work worth a wave (0 = keep). */
+int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes);
 
 /* ---------------------------------------------------------------------- */
 /* Hashing a batch (Algorithm 1 with Eq. (1) blocks, Sec. 4 byte padding,

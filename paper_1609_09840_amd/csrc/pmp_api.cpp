@@ -54,9 +54,10 @@ struct pmp_plan {
   int32_t* status = nullptr;  // device
   pmp::Slot* slots = nullptr;  // device
   uint64_t nslots = 0;
-  int g32 = 8, g64 = 8;
-  uint32_t alpha = 64;       // per-string work in byte equivalents
+  int g32 = 8, g64 = 16;
+  uint32_t alpha = 64;         // per-string work in byte equivalents
   uint64_t wave_bytes = 8192;  // smallest share of work worth a wave
+  int waves_per_cu = 0;        // 0: as many as stay resident
   int cus = 0;
   std::mutex mu;
 };
@@ -196,7 +197,10 @@ int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStr
   a.status = plan->status;
 
   // one wave per `wave_bytes` of work, at most what the device keeps resident
-  const uint64_t max_waves = (uint64_t)plan->cus * 16;
+  int per_cu = plan->waves_per_cu;
+  if (per_cu <= 0) per_cu = 4 * pmp::batch_blocks_per_cu(plan->g32, plan->g64);
+  if (per_cu <= 0) per_cu = 8;
+  const uint64_t max_waves = (uint64_t)plan->cus * (uint64_t)per_cu;
   uint64_t waves = (work + plan->wave_bytes - 1) / plan->wave_bytes;
   if (waves < 1) waves = 1;
   if (waves > max_waves) waves = max_waves;
@@ -316,12 +320,22 @@ int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream) {
 
 int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block) {
   if (!plan) return fail(PMP_E_INVALID_ARG, "plan is NULL");
-  if (lanes_per_block == 0) lanes_per_block = 8;
-  if (!pmp::batch_tile_supported(lanes_per_block))
-    return fail(PMP_E_INVALID_ARG, "lanes per block must be 4, 8 or 16 (got %d)", lanes_per_block);
   std::lock_guard<std::mutex> lk(plan->mu);
-  if (wide) plan->g64 = lanes_per_block;
-  else plan->g32 = lanes_per_block;
+  const int g32 = wide ? plan->g32 : (lanes_per_block ? lanes_per_block : 8);
+  const int g64 = wide ? (lanes_per_block ? lanes_per_block : 16) : plan->g64;
+  if (!pmp::batch_tiles_supported(g32, g64))
+    return fail(PMP_E_INVALID_ARG, "no kernel for %d (PM+32) and %d (PM+64) lanes per block", g32, g64);
+  plan->g32 = g32;
+  plan->g64 = g64;
+  return PMP_OK;
+}
+
+int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes) {
+  if (!plan || waves_per_cu < 0 || waves_per_cu > 64) return fail(PMP_E_INVALID_ARG, "bad tuning values");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  plan->waves_per_cu = waves_per_cu;
+  if (alpha) plan->alpha = alpha;
+  if (wave_bytes) plan->wave_bytes = wave_bytes;
   return PMP_OK;
 }
 

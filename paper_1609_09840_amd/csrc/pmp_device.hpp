@@ -198,6 +198,37 @@ __device__ __forceinline__ uint64_t shx(uint64_t v, int m) {
 __device__ __forceinline__ S32 shx(const S32& s, int m) { return S32{shx(s.lo, m), shx(s.hi, m)}; }
 __device__ __forceinline__ S64 shx(const S64& s, int m) { return S64{shx(s.w0, m), shx(s.w1, m), shx(s.w2, m)}; }
 
+// DPP lane moves within a row of 16 lanes (no LDS traffic):
+//   0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm [2,3,0,1] (lane ^ 2),
+//   0x141 row_half_mirror (i -> 7 - i in each 8), 0x140 row_mirror (i -> 15 - i)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp(uint64_t v) {
+  return ((uint64_t)dpp<CTRL>((uint32_t)(v >> 32)) << 32) | dpp<CTRL>((uint32_t)v);
+}
+template <int CTRL>
+__device__ __forceinline__ S32 dpp(const S32& s) {
+  return S32{dpp<CTRL>(s.lo), dpp<CTRL>(s.hi)};
+}
+template <int CTRL>
+__device__ __forceinline__ S64 dpp(const S64& s) {
+  return S64{dpp<CTRL>(s.w0), dpp<CTRL>(s.w1), dpp<CTRL>(s.w2)};
+}
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8, 16); every lane of a
+// group ends with the group's sum. After the two quad steps each quad holds
+// its sum, so mirroring within 8 (then 16) lanes pairs each lane with the
+// other half.
+template <int G, class S>
+__device__ __forceinline__ void group_sum(S& s) {
+  if constexpr (G >= 2) add(s, dpp<0xB1>(s));
+  if constexpr (G >= 4) add(s, dpp<0x4E>(s));
+  if constexpr (G >= 8) add(s, dpp<0x141>(s));
+  if constexpr (G >= 16) add(s, dpp<0x140>(s));
+}
+
 template <class S>
 __device__ __forceinline__ void reduce_lanes(S& s, int from, int to) {
   for (int m = from; m < to; m <<= 1) {
@@ -248,16 +279,13 @@ __device__ __forceinline__ Q load16(const uint8_t* a) {
   __builtin_memcpy(q.d, __builtin_assume_aligned(a, 4), 16);
   return q;
 }
-__device__ __noinline__ Q load16_slow(const uint8_t* a, const uint8_t* lo, const uint8_t* hi) {
-  Q q;
-  for (int u = 0; u < 4; ++u) {
-    uint32_t v = 0;
-    for (int t = 0; t < 4; ++t) {
-      const uint8_t* p = a + 4 * u + t;
-      uint32_t byte = (p >= lo && p < hi) ? (uint32_t)*p : 0u;
-      v |= byte << (8 * t);
-    }
-    q.d[u] = v;
+__device__ __forceinline__ Q load16_slow(const uint8_t* a, const uint8_t* lo, const uint8_t* hi) {
+  Q q = {{0, 0, 0, 0}};
+#pragma unroll 1
+  for (int t = 0; t < 16; ++t) {
+    const uint8_t* p = a + t;
+    const uint32_t byte = (p >= lo && p < hi) ? (uint32_t)*p : 0u;
+    q.d[t >> 2] |= byte << (8 * (t & 3));
   }
   return q;
 }
@@ -268,6 +296,7 @@ __device__ __forceinline__ Q load16_guarded(const uint8_t* a, const uint8_t* lo,
 __device__ __forceinline__ uint32_t load4_guarded(const uint8_t* a, const uint8_t* lo, const uint8_t* hi) {
   if (a >= lo && a + 4 <= hi) return *(const uint32_t*)__builtin_assume_aligned(a, 4);
   uint32_t v = 0;
+#pragma unroll 1
   for (int t = 0; t < 4; ++t) {
     const uint8_t* p = a + t;
     v |= ((p >= lo && p < hi) ? (uint32_t)*p : 0u) << (8 * t);

@@ -12,12 +12,12 @@ constexpr uint32_t FLAG_OUT_FIELD = 2u;
 constexpr int32_t STATUS_OFFSETS = 1;   // an offsets pair was out of order or out of range
 constexpr int32_t STATUS_INTERNAL = 2;  // a node accumulator fell outside the workspace
 
-// Accumulator of one tree node (level >= 2): a sum of field elements
-// lo + 2^64 hi and the weight received so far. All zero between launches.
+// Accumulator of one tree node (level >= 2), all zero between launches.
+// PM+32: w0 = (weight received << 56) | sum of field elements (< 2^40).
+// PM+64: w0 = low 64 bits of the sum, w1 = (weight << 32) | high bits.
 struct Slot {
-  uint64_t lo;
-  uint32_t hi;
-  uint32_t cnt;
+  uint64_t w0;
+  uint64_t w1;
 };
 
 // One batch as the kernel sees it.
@@ -44,7 +44,8 @@ struct KArgs {
 
 // kernels/launchers (pmp_kernels.hip)
 hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s);
-bool batch_tile_supported(int g);
+int batch_blocks_per_cu(int g32, int g64);       // resident 256-thread blocks per CU
+bool batch_tiles_supported(int g32, int g64);    // compiled lanes-per-block pairs
 hipError_t launch_plain_string(int wide, const uint8_t* buf, uint64_t buf_bytes, int64_t o0, int64_t len,
                                const void* keys, void* out, int64_t index, uint32_t flags, uint4* scratch,
                                uint64_t scratch_slots, hipStream_t s);

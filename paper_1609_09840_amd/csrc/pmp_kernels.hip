@@ -95,18 +95,49 @@ __device__ __forceinline__ void store_out(const BatchArgs& B, int64_t i, const F
 }
 
 // ---------------------------------------------------------------------------
+// Loads that are issued together. A piece whose bytes are not all inside
+// [lo, hi) reads 16 bytes at `safe` instead (any readable address; the key
+// table serves) so that every lane's load can be in flight at once; such
+// pieces are zeroed, and the rare ones that straddle lo or hi are read again
+// byte by byte afterwards.
+__device__ __forceinline__ bool inside(const uint8_t* a, int n, const uint8_t* lo, const uint8_t* hi) {
+  return a >= lo && a + n <= hi;
+}
+
+// Word u (0..3) of a 16-byte group held in dwords d[0..4], realigned by sh
+// bytes, masked to the padded string (Sec. 4): r = string bytes from the
+// start of the group's first word (negative: past the padded end).
+template <bool WIDE>
+__device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int64_t r, uint32_t* x) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
+  if constexpr (WIDE) {
+    tail_word64(x[0], x[1], r);
+    tail_word64(x[2], x[3], r < 0 ? r : r - 8);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = tail_word32(x[u], r < 0 ? r : r - 4 * u);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Strings of one block, one per lane. `act` marks lanes with such a string.
+// Each lane walks its string in batches of K 16-byte groups whose loads are
+// all in flight together; the group's keys are wave-uniform scalar loads.
 template <bool WIDE>
 __device__ void short_strings(const BatchArgs& B, int64_t i, bool act, int64_t o0, int64_t len) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
   constexpr int WPG = 16 / W;  // words per 16-byte group
+  constexpr int K = 8;         // groups per batch of loads
   const uint8_t* lo = B.buf;
   const uint8_t* hi = B.buf + B.buf_bytes;
+  const uint8_t* safe = (const uint8_t*)B.keys;
   const uint8_t* s = B.buf + (act ? o0 : 0);
   const uint32_t sh = (uint32_t)((uintptr_t)s & 3u);
   const uint8_t* a4 = s - sh;
   const int64_t nw = act ? len / W + 1 : 0;
+  const int64_t rlen = act ? len : -1;  // inactive lanes mask every word away
   const uint32_t ng = (uint32_t)((nw + WPG - 1) / WPG);
   const uint32_t maxg = wave_max(ng);
   if (maxg == 0) return;
@@ -116,38 +147,56 @@ __device__ void short_strings(const BatchArgs& B, int64_t i, bool act, int64_t o
   zero(acc);
   P64 p;
   zero(p);
-  Q cur = {{0, 0, 0, 0}};
-  if (act) cur = load16_guarded(a4, lo, hi);
-  for (uint32_t g = 0; g < maxg; ++g) {
-    if (g < ng) {
-      const uint8_t* nxa = a4 + 16 * (int64_t)(g + 1);
-      Q nxt = {{0, 0, 0, 0}};
-      if (g + 1 < ng) nxt = load16_guarded(nxa, lo, hi);
-      else if (sh) nxt.d[0] = load4_guarded(nxa, lo, hi);
-      uint32_t d[5] = {cur.d[0], cur.d[1], cur.d[2], cur.d[3], nxt.d[0]};
-      uint32_t x[4];
+  for (uint32_t g0 = 0; g0 < maxg; g0 += K) {
+    uint32_t d[4 * K + 1];
+    uint32_t part = 0;  // groups that straddle the buffer edges
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
-      if (g + 1 == ng) {
-        const int64_t r0 = len - 16 * (int64_t)g;
-        if constexpr (WIDE) {
-          tail_word64(x[0], x[1], r0);
-          tail_word64(x[2], x[3], r0 - 8);
-        } else {
+    for (int k = 0; k < K; ++k) {
+      const uint32_t g = g0 + k;
+      const uint8_t* pa = a4 + 16 * (int64_t)g;
+      // the group after the last one supplies the last group's realignment
+      const bool need = g < ng + (sh ? 1u : 0u);
+      const bool full = need && inside(pa, 16, lo, hi);
+      Q q = load16(full ? pa : safe);
+      if (need && !full) part |= 1u << k;
+      d[4 * k] = full ? q.d[0] : 0u;
+      d[4 * k + 1] = full ? q.d[1] : 0u;
+      d[4 * k + 2] = full ? q.d[2] : 0u;
+      d[4 * k + 3] = full ? q.d[3] : 0u;
+    }
+    {  // first dword after the batch (realignment of the last group)
+      const uint8_t* pa = a4 + 16 * (int64_t)(g0 + K);
+      const bool need = sh && g0 + K - 1 < ng;
+      const bool full = need && inside(pa, 4, lo, hi);
+      const uint32_t e = *(const uint32_t*)__builtin_assume_aligned(full ? pa : safe, 4);
+      d[4 * K] = full ? e : (need ? load4_guarded(pa, lo, hi) : 0u);
+    }
+    if (part) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = tail_word32(x[u], r0 - 4 * u);
+      for (int k = 0; k < K; ++k)
+        if (part & (1u << k)) {
+          Q q = load16_slow(a4 + 16 * (int64_t)(g0 + k), lo, hi);
+          d[4 * k] = q.d[0];
+          d[4 * k + 1] = q.d[1];
+          d[4 * k + 2] = q.d[2];
+          d[4 * k + 3] = q.d[3];
         }
-      }
-      if constexpr (WIDE) {
-        const uint64_t* k = keys + 2 * g;
-        mac64_sv(p, k[0], x[0], x[1]);
-        mac64_sv(p, k[1], x[2], x[3]);
-      } else {
-        const uint32_t* k = keys + 4 * g;
+    }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) mac_sv(acc.lo, acc.hi, k[u], x[u]);
+    for (int k = 0; k < K; ++k) {
+      const uint32_t g = g0 + k;
+      if (g >= maxg) break;  // uniform
+      uint32_t x[4];
+      group_words<WIDE>(d + 4 * k, sh, rlen - 16 * (int64_t)g, x);
+      if constexpr (WIDE) {
+        const uint64_t* kk = keys + 2 * g;
+        mac64_sv(p, kk[0], x[0], x[1]);
+        mac64_sv(p, kk[1], x[2], x[3]);
+      } else {
+        const uint32_t* kk = keys + 4 * g;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mac_sv(acc.lo, acc.hi, kk[u], x[u]);
       }
-      cur = nxt;
     }
   }
   if (act) {
@@ -160,59 +209,39 @@ __device__ void short_strings(const BatchArgs& B, int64_t i, bool act, int64_t o
 }
 
 // ---------------------------------------------------------------------------
-// Tree shape of a string with C1 level-1 blocks (Algorithm 1): level j
-// produces n[j] values, n[j+1] = ceil(n[j] / 128), until one value remains.
-// Every node of level >= 2 owns one accumulator slot; the string's slots
-// start at ceil(o0 / (128 W)) and are laid out level by level.
-struct Levels {
-  int L;
-  uint64_t n[LMAX + 2];
-  uint64_t off[LMAX + 2];  // slot offset of level j (j >= 2)
-};
-__device__ __forceinline__ Levels levels_of(uint64_t C1) {
-  Levels t;
-  t.n[1] = C1;
-  int L = 1;
-  while (t.n[L] > 1 && L <= LMAX) {
-    t.n[L + 1] = (t.n[L] + BLOCK - 1) / BLOCK;
-    ++L;
-  }
-  t.L = L;
-  uint64_t o = 0;
-  for (int j = 2; j <= L; ++j) {
-    t.off[j] = o;
-    o += t.n[j];
-  }
-  return t;
-}
-
-// A field element z as a number lo + 2^64 hi.
+// Node accumulators. Each node of level >= 2 that is not finished by a single
+// wave owns one Slot; a string's slots start at ceil(o0 / (128 W)), level by
+// level (level 2 first). Contributions are field elements; the call that
+// brings the received weight to `target` gets the node's total (a sum of at
+// most 128 field elements, lo + 2^64 hi), leaves the slot zeroed for the next
+// launch and returns true. Only atomic read-modify-writes touch a slot, and a
+// wave issues its second one only after the first has returned (its operand
+// depends on the result), so no fence is needed: the completing wave's final
+// exchange comes after every contribution in each word's order. Lane 0 only.
 template <bool WIDE>
-__device__ __forceinline__ uint64_t fe_lo(const Fe& z) {
-  return WIDE ? z.lo : (z.lo | ((uint64_t)z.hi << 32));
-}
-template <bool WIDE>
-__device__ __forceinline__ uint32_t fe_hi(const Fe& z) {
-  return WIDE ? z.hi : 0u;
-}
-
-// Add a field element (< p) with weight `weight` to a node accumulator. The
-// call that brings the weight to `target` gets true and the node's total
-// (a sum of at most 128 field elements) in *tot, and returns the slot to
-// zero for the next launch. Called by lane 0 only.
-__device__ __forceinline__ bool contribute(Slot* sl, uint64_t clo, uint32_t chi, uint32_t weight, uint32_t target,
-                                           uint64_t* tlo, uint32_t* thi) {
-  const uint64_t old = __hip_atomic_fetch_add(&sl->lo, clo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint32_t carry = (old + clo < old) ? 1u : 0u;
-  if (carry + chi) __hip_atomic_fetch_add(&sl->hi, carry + chi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint32_t before = __hip_atomic_fetch_add(&sl->cnt, weight, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  if (before + weight != target) return false;
-  *tlo = __hip_atomic_load(&sl->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  *thi = __hip_atomic_load(&sl->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&sl->lo, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&sl->hi, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&sl->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
+__device__ __forceinline__ bool contribute(Slot* sl, const Fe& c, uint32_t weight, uint32_t target, uint64_t* tlo,
+                                           uint32_t* thi) {
+  if constexpr (!WIDE) {
+    constexpr uint64_t M56 = (1ull << 56) - 1;
+    const uint64_t v = c.lo | ((uint64_t)c.hi << 32);  // < 2^33
+    const uint64_t old =
+        __hip_atomic_fetch_add(&sl->w0, ((uint64_t)weight << 56) + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(old >> 56) + weight != target) return false;
+    __hip_atomic_store(&sl->w0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *tlo = (old & M56) + v;
+    *thi = 0;
+    return true;
+  } else {
+    const uint64_t old0 = __hip_atomic_fetch_add(&sl->w0, c.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t carry = (old0 + c.lo < old0) ? 1u : 0u;
+    const uint64_t add1 = ((uint64_t)weight << 32) | (uint64_t)(c.hi + carry);
+    const uint64_t old1 = __hip_atomic_fetch_add(&sl->w1, add1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(old1 >> 32) + weight != target) return false;
+    *tlo = __hip_atomic_exchange(&sl->w0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&sl->w1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *thi = (uint32_t)old1 + c.hi + carry;
+    return true;
+  }
 }
 
 template <bool WIDE>
@@ -230,59 +259,158 @@ __device__ __forceinline__ Fe reduce_total(uint64_t lo, uint32_t hi, uint64_t b)
   return reduce(s);
 }
 
-// A node value v at level j (index k) of string i is known: move up the tree.
-// The parent's accumulator receives (a_{j+1, k mod 128} * v) mod p; whoever
-// completes a parent computes it (adding b_{j+1}) and carries on. The root
-// is written to the output. Wave-uniform arguments.
+__device__ __forceinline__ uint64_t up(uint64_t n) { return (n + BLOCK - 1) / BLOCK; }
+
+// Levels of a string with C1 blocks (Algorithm 1): n_1 = C1, n_{j+1} =
+// ceil(n_j / 128), down to one value.
+__device__ __forceinline__ int levels_of(uint64_t C1) {
+  int L = 1;
+  for (uint64_t n = C1; n > 1; n = up(n)) ++L;
+  return L;
+}
+
+// The value v of node k on level 2 of string i is known; n2 = number of
+// level-2 nodes. Move up the tree: the parent's accumulator receives
+// (a_{j+1, k mod 128} * v) mod p; the wave that completes a parent computes
+// it (adding b_{j+1}) and carries on; the root goes to the output.
 template <bool WIDE>
-__device__ void climb(const KArgs& A, const BatchArgs& B, int64_t i, uint64_t sbase, const Levels& t, int j,
-                      uint64_t k, Fe v) {
+__device__ void climb(const KArgs& A, const BatchArgs& B, int64_t i, uint64_t sbase, uint64_t n2, uint64_t k, Fe v) {
   using T = Tr<WIDE>;
   const typename T::key_t* keys = (const typename T::key_t*)B.keys;
+  int j = 2;
+  uint64_t nj = n2;    // values on level j
+  uint64_t offj = 0;   // first slot of level j
   while (true) {
-    if (j == t.L) {
+    if (nj == 1) {  // level j is the root
       if (lane_id() == 0) store_out<WIDE>(B, i, v);
       return;
     }
     const uint64_t parent = k / BLOCK;
-    const uint64_t nch = t.n[j] - parent * BLOCK < (uint64_t)BLOCK ? t.n[j] - parent * BLOCK : (uint64_t)BLOCK;
+    const uint64_t nch = nj - parent * BLOCK < (uint64_t)BLOCK ? nj - parent * BLOCK : (uint64_t)BLOCK;
     typename T::Sum pr;
     zero(pr);
     mac_fe(pr, keys[(uint64_t)j * BLOCK + (k - parent * BLOCK)], v);  // level j+1 keys
     const Fe c = reduce(pr);
-    const uint64_t si = sbase + t.off[j + 1] + parent;
+    const uint64_t si = sbase + offj + nj + parent;  // slot of the parent on level j+1
     uint32_t done = 0;
     uint64_t tlo = 0;
     uint32_t thi = 0;
     if (lane_id() == 0) {
-      if (si < B.nslots)
-        done = contribute((Slot*)B.slots + si, fe_lo<WIDE>(c), fe_hi<WIDE>(c), 1u, (uint32_t)nch, &tlo, &thi) ? 1u : 0u;
+      if (si < B.nslots) done = contribute<WIDE>(B.slots + si, c, 1u, (uint32_t)nch, &tlo, &thi) ? 1u : 0u;
       else __hip_atomic_fetch_or(A.status, STATUS_INTERNAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!uni(done)) return;
     v = reduce_total<WIDE>(uni64(tlo), uni(thi), (uint64_t)keys[8 * BLOCK + j]);
+    offj += nj;
+    nj = up(nj);
     ++j;
     k = parent;
   }
 }
 
-// Exact sum over blocks c in [bl, bh) of level-2 node `node` of
-// a_{2, c - 128 node} * f_1(block c), for a string of len bytes at s with C1
-// blocks. G lanes per block: lane j of a group owns words [j*128/G,
-// (j+1)*128/G) of its block, with those level-1 keys in registers. Every lane
-// returns the whole wave's sum.
+// Partial block sum of one lane: lane j of a G-lane group owns the 16-byte
+// pieces j, j + G, j + 2G, ... of its block, so for each load the G lanes of
+// a group read 16 G contiguous bytes. blk is the block start moved back by sh
+// (4-aligned); piece P is bytes [16 P, 16 P + 16) of the block, read as
+// dwords D0..D4 at blk + 16 P and realigned by sh bytes. lk holds the
+// level-1 keys in LDS (as 64-bit words). All loads are issued before the
+// first product so that they are in flight together. TAIL: the block may be
+// inactive (act) or run past the string end (rem = string bytes from the
+// block start); its words are masked to the padded string of Sec. 4. The
+// caller guarantees that every byte read lies inside the buffer.
+template <bool WIDE, int G, bool TAIL>
+__device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const uint8_t* blk, int j, uint32_t sh,
+                                                            const uint64_t* lk, bool act, int64_t rem) {
+  using T = Tr<WIDE>;
+  constexpr int W = T::W;
+  constexpr int WPP = 16 / W;             // words per piece
+  constexpr int NL = BLOCK * W / 16 / G;  // pieces per lane
+  uint32_t d[NL][5];
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const uint8_t* pa = blk + 16 * (t * G + j);
+    Q q = load16(pa);
+    d[t][0] = q.d[0];
+    d[t][1] = q.d[1];
+    d[t][2] = q.d[2];
+    d[t][3] = q.d[3];
+    d[t][4] = sh ? *(const uint32_t*)__builtin_assume_aligned(pa + 16, 4) : 0u;
+  }
+  const int64_t r = act ? rem : -(int64_t)(BLOCK * W) - 64;  // inactive: everything masked
+  typename T::Sum acc;
+  P64 p;
+  zero(acc);
+  zero(p);
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    uint32_t x[4];
+    if constexpr (TAIL) {
+      group_words<WIDE>(d[t], sh, r - 16 * (int64_t)(t * G + j), x);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[t][u + 1], d[t][u], sh);
+    }
+    const uint64_t* kp = lk + WPP * (t * G + j);
+    if constexpr (WIDE) {
+      mac64_vv(p, kp[0], x[0], x[1]);
+      mac64_vv(p, kp[1], x[2], x[3]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mac_vv(acc.lo, acc.hi, (uint32_t)kp[u], x[u]);
+    }
+  }
+  if constexpr (WIDE) acc = collapse(p);
+  return acc;
+}
+
+// The same for a step that touches the buffer edges (only possible at the
+// very start or end of the buffer): one piece at a time, every byte checked.
 template <bool WIDE, int G>
-__device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint8_t* s, int64_t len, int64_t C1,
+__device__ typename Tr<WIDE>::Sum block_guarded(const uint8_t* blk, int j, uint32_t sh, const uint64_t* lk, bool act,
+                                                int64_t rem, const uint8_t* lo, const uint8_t* hi) {
+  using T = Tr<WIDE>;
+  constexpr int W = T::W;
+  constexpr int WPP = 16 / W;
+  constexpr int NL = BLOCK * W / 16 / G;
+  const int64_t r = act ? rem : -(int64_t)(BLOCK * W) - 64;
+  typename T::Sum acc;
+  P64 p;
+  zero(acc);
+  zero(p);
+#pragma unroll 1
+  for (int t = 0; t < NL; ++t) {
+    const int P = t * G + j;
+    const int64_t rp = r - 16 * (int64_t)P;
+    if (rp < 0) continue;  // the piece lies past the padded string
+    const uint8_t* pa = blk + 16 * P;
+    const Q q = load16_guarded(pa, lo, hi);
+    const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], sh ? load4_guarded(pa + 16, lo, hi) : 0u};
+    uint32_t x[4];
+    group_words<WIDE>(d, sh, rp, x);
+    const uint64_t* kp = lk + WPP * P;
+    if constexpr (WIDE) {
+      mac64_vv(p, kp[0], x[0], x[1]);
+      mac64_vv(p, kp[1], x[2], x[3]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mac_vv(acc.lo, acc.hi, (uint32_t)kp[u], x[u]);
+    }
+  }
+  if constexpr (WIDE) acc = collapse(p);
+  return acc;
+}
+
+// Exact sum over blocks c in [bl, bh) of level-2 node `node` of
+// a_{2, c - 128 node} * f_1(block c), for a string of len bytes at s, G lanes
+// per block. Every lane returns the whole wave's sum.
+template <bool WIDE, int G>
+__device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint64_t* lk, const uint8_t* s, int64_t len,
                                               int64_t node, int64_t bl, int64_t bh) {
   using T = Tr<WIDE>;
-  using key_t = typename T::key_t;
   using Sum = typename T::Sum;
   constexpr int W = T::W;
-  constexpr int WPL = BLOCK / G;  // words per lane per block
-  constexpr int BPL = WPL * W;    // bytes per lane per block
-  constexpr int NL = BPL / 16;    // 16-byte loads per lane per block
-  constexpr int ND = BPL / 4;     // dwords per lane per block
-  constexpr int CPS = 64 / G;     // blocks per wave step
+  constexpr int NL = BLOCK * W / 16 / G;
+  constexpr int CPS = 64 / G;  // blocks per wave step
   static_assert(NL >= 1, "tile too wide");
   const int lane = lane_id();
   const int g = lane / G, j = lane % G;
@@ -290,75 +418,30 @@ __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint8_t*
   const uint8_t* hi = B.buf + B.buf_bytes;
   const uint32_t sh = uni((uint32_t)((uintptr_t)s & 3u));
   const uint8_t* a4 = s - sh;
-  const key_t* __restrict__ keys = (const key_t*)B.keys;
   const int64_t nb = node * BLOCK;
-
-  key_t kr[WPL];
-#pragma unroll
-  for (int u = 0; u < WPL; ++u) kr[u] = keys[j * WPL + u];
-  const key_t b1 = keys[8 * BLOCK];
+  const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
 
   Sum acc2;
   zero(acc2);
   for (int64_t c0 = bl; c0 < bh; c0 += CPS) {
+    // keys stay in LDS: reading them again each step keeps registers free
+    asm volatile("" ::: "memory");
     const int64_t c = c0 + g;
     const bool act = c < bh;
-    const int64_t off = c * (int64_t)(BLOCK * W) + (int64_t)j * BPL;
+    const uint8_t* blk = a4 + c * (int64_t)(BLOCK * W);
     const uint8_t* step_lo = a4 + c0 * (int64_t)(BLOCK * W);
     const uint8_t* step_hi = a4 + (c0 + CPS) * (int64_t)(BLOCK * W) + 4;
-    const bool edge = (c0 + CPS >= bh) || step_lo < lo || step_hi > hi;  // uniform
-    uint32_t d[ND + 1];
-    if (!edge) {
-#pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        Q q = load16(a4 + off + 16 * l);
-        d[4 * l] = q.d[0];
-        d[4 * l + 1] = q.d[1];
-        d[4 * l + 2] = q.d[2];
-        d[4 * l + 3] = q.d[3];
-      }
-      d[ND] = sh ? *(const uint32_t*)__builtin_assume_aligned(a4 + off + BPL, 4) : 0u;
-    } else {
-#pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        Q q = {{0, 0, 0, 0}};
-        // bytes from the string end on are masked below, so skip such loads
-        if (act && off + 16 * l < len + 4) q = load16_guarded(a4 + off + 16 * l, lo, hi);
-        d[4 * l] = q.d[0];
-        d[4 * l + 1] = q.d[1];
-        d[4 * l + 2] = q.d[2];
-        d[4 * l + 3] = q.d[3];
-      }
-      d[ND] = (act && sh && off + BPL < len + 4) ? load4_guarded(a4 + off + BPL, lo, hi) : 0u;
-    }
-    uint32_t x[ND];
-#pragma unroll
-    for (int u = 0; u < ND; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
-    if (edge) {
-      const int64_t w0 = c * BLOCK + (int64_t)j * WPL;  // first word of this lane
-#pragma unroll
-      for (int u = 0; u < WPL; ++u) {
-        const int64_t r = act ? len - (int64_t)W * (w0 + u) : -1;
-        if constexpr (WIDE) tail_word64(x[2 * u], x[2 * u + 1], r);
-        else x[u] = tail_word32(x[u], r);
-      }
-    }
-    Sum blk;
-    if constexpr (WIDE) {
-      P64 p;
-      zero(p);
-#pragma unroll
-      for (int u = 0; u < WPL; ++u) mac64_vv(p, kr[u], x[2 * u], x[2 * u + 1]);
-      blk = collapse(p);
-    } else {
-      zero(blk);
-#pragma unroll
-      for (int u = 0; u < WPL; ++u) mac_vv(blk.lo, blk.hi, kr[u], x[u]);
-    }
-    reduce_lanes(blk, 1, G);
-    add_word(blk, (uint64_t)b1);
-    const Fe z = reduce(blk);
-    if (act) mac_fe(acc2, keys[BLOCK + (c - nb)], z);
+    const bool tail = c0 + CPS >= bh;                // uniform
+    const bool out = step_lo < lo || step_hi > hi;   // uniform, only at the buffer edges
+    const int64_t rem = len - c * (int64_t)(BLOCK * W);
+    Sum blk_sum;
+    if (out) blk_sum = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
+    else if (tail) blk_sum = block_sum<WIDE, G, true>(blk, j, sh, lk, act, rem);
+    else blk_sum = block_sum<WIDE, G, false>(blk, j, sh, lk, true, 0);
+    group_sum<G>(blk_sum);
+    add_word(blk_sum, b1);
+    const Fe z = reduce(blk_sum);
+    if (act) mac_fe(acc2, (typename T::key_t)lk[BLOCK + (c - nb)], z);
   }
   reduce_lanes(acc2, G, 64);
   return acc2;
@@ -366,17 +449,17 @@ __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint8_t*
 
 // Blocks [lo_c, hi_c) of one string with C1 >= 2 blocks, by the whole wave.
 template <bool WIDE, int G>
-__device__ void long_string(const KArgs& A, const BatchArgs& B, int64_t i, int64_t o0, int64_t len, int64_t C1,
-                            int64_t lo_c, int64_t hi_c) {
+__device__ void long_string(const KArgs& A, const BatchArgs& B, const uint64_t* lk, int64_t i, int64_t o0,
+                            int64_t len, int64_t C1, int64_t lo_c, int64_t hi_c) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
   const typename T::key_t* keys = (const typename T::key_t*)B.keys;
   const uint8_t* s = B.buf + o0;
-  const Levels t = levels_of((uint64_t)C1);
-  if (t.L > LMAX) {  // more than 8 levels (over 2^56 words)
+  if (levels_of((uint64_t)C1) > LMAX) {  // more than 8 levels (over 2^56 words)
     if (lane_id() == 0) __hip_atomic_fetch_or(A.status, STATUS_OFFSETS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
+  const uint64_t n2 = up((uint64_t)C1);
   const uint64_t sbase = ((uint64_t)o0 + BLOCK * W - 1) / (BLOCK * W);
   const uint64_t b2 = (uint64_t)keys[8 * BLOCK + 1];
   for (int64_t n = lo_c / BLOCK; n * BLOCK < hi_c; ++n) {
@@ -384,29 +467,26 @@ __device__ void long_string(const KArgs& A, const BatchArgs& B, int64_t i, int64
     const int64_t nhi = (C1 < nlo + BLOCK) ? C1 : nlo + BLOCK;
     const int64_t bl = lo_c > nlo ? lo_c : nlo;
     const int64_t bh = hi_c < nhi ? hi_c : nhi;
-    typename T::Sum part = node_blocks<WIDE, G>(B, s, len, C1, n, bl, bh);
+    typename T::Sum part = node_blocks<WIDE, G>(B, lk, s, len, n, bl, bh);
     Fe v;
     if (bl == nlo && bh == nhi) {  // the whole node is here
       add_word(part, b2);
       v = reduce(part);
     } else {  // pieces of this node are hashed by neighbouring waves too
       const Fe c = reduce(part);
-      const uint64_t si = sbase + t.off[2] + (uint64_t)n;
+      const uint64_t si = sbase + (uint64_t)n;
       uint32_t done = 0;
       uint64_t tlo = 0;
       uint32_t thi = 0;
       if (lane_id() == 0) {
         if (si < B.nslots)
-          done = contribute((Slot*)B.slots + si, fe_lo<WIDE>(c), fe_hi<WIDE>(c), (uint32_t)(bh - bl),
-                            (uint32_t)(nhi - nlo), &tlo, &thi)
-                     ? 1u
-                     : 0u;
+          done = contribute<WIDE>(B.slots + si, c, (uint32_t)(bh - bl), (uint32_t)(nhi - nlo), &tlo, &thi) ? 1u : 0u;
         else __hip_atomic_fetch_or(A.status, STATUS_INTERNAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (!uni(done)) continue;
       v = reduce_total<WIDE>(uni64(tlo), uni(thi), b2);
     }
-    climb<WIDE>(A, B, i, sbase, t, 2, (uint64_t)n, v);
+    climb<WIDE>(A, B, i, sbase, n2, (uint64_t)n, v);
   }
 }
 
@@ -464,7 +544,7 @@ __device__ Pos locate(const BatchArgs& B, uint32_t alpha, uint64_t x) {
 
 // All blocks in [ps, pe) of one batch, 64 strings at a time.
 template <bool WIDE, int G>
-__device__ void run_range(const KArgs& A, const BatchArgs& B, Pos ps, Pos pe) {
+__device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk, Pos ps, Pos pe) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
   const int lane = lane_id();
@@ -494,23 +574,33 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, Pos ps, Pos pe) {
 
     short_strings<WIDE>(B, i, shrt, o0, len);
 
+    // the long strings, one at a time by the whole wave; their offsets are
+    // read again as scalars rather than kept in vector registers
     uint64_t m = __ballot(lng);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const int64_t si = uni64s(__shfl((long long)i, l, 64));
-      const int64_t so = uni64s(__shfl((long long)o0, l, 64));
-      const int64_t sl = uni64s(__shfl((long long)len, l, 64));
-      const int64_t sc = uni64s(__shfl((long long)C1, l, 64));
-      const int64_t slo = uni64s(__shfl((long long)lo_c, l, 64));
-      const int64_t shi = uni64s(__shfl((long long)hi_c, l, 64));
-      long_string<WIDE, G>(A, B, si, so, sl, sc, slo, shi);
+      const int64_t si = t0 + l;
+      const int64_t so = B.offsets[si];
+      const int64_t sl = B.offsets[si + 1] - so;
+      const int64_t sc = ((sl / W + 1) + BLOCK - 1) / BLOCK;
+      const int64_t slo = (si == ps.i) ? ps.c : 0;
+      const int64_t shi = (si == pe.i) ? pe.c : sc;
+      long_string<WIDE, G>(A, B, lk, si, so, sl, sc, slo, shi);
     }
   }
 }
 
 template <int G32, int G64>
 __global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
+  // level-1 and level-2 keys of each batch, as 64-bit words, shared by the
+  // workgroup's four waves
+  __shared__ uint64_t lkeys[2][2 * BLOCK];
+  for (uint32_t b = 0; b < A.nbatch; ++b) {
+    const BatchArgs& B = A.b[b];
+    lkeys[b][threadIdx.x] = B.wide ? ((const uint64_t*)B.keys)[threadIdx.x] : ((const uint32_t*)B.keys)[threadIdx.x];
+  }
+  __syncthreads();
   const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (w >= A.total_waves) return;
   uint64_t work[2] = {0, 0};
@@ -533,17 +623,15 @@ __global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
       const BatchArgs& B = A.b[b];
       if (B.wide) {
         const Pos ps = locate<8>(B, A.alpha, lo - bstart), pe = locate<8>(B, A.alpha, hi - bstart);
-        run_range<true, G64>(A, B, ps, pe);
+        run_range<true, G64>(A, B, lkeys[b], ps, pe);
       } else {
         const Pos ps = locate<4>(B, A.alpha, lo - bstart), pe = locate<4>(B, A.alpha, hi - bstart);
-        run_range<false, G32>(A, B, ps, pe);
+        run_range<false, G32>(A, B, lkeys[b], ps, pe);
       }
     }
     bstart = bend;
   }
 }
-
-bool batch_tile_supported(int g) { return g == 4 || g == 8 || g == 16; }
 
 template <int G32, int G64>
 static hipError_t launch_t(const KArgs& a, int grid, hipStream_t s) {
@@ -551,20 +639,37 @@ static hipError_t launch_t(const KArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int G32, int G64>
+static int occupancy_t() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<G32, G64>, 256, 0) != hipSuccess) return 0;
+  return n;
+}
+
+#define PMP_TILES(X) X(8, 16) X(8, 8) X(16, 16) X(4, 16) X(16, 8) X(4, 8)
+
 hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s) {
 #define PMP_CASE(X, Y) \
   if (g32 == X && g64 == Y) return launch_t<X, Y>(a, grid, s);
-  PMP_CASE(8, 8)
-  PMP_CASE(4, 4)
-  PMP_CASE(4, 8)
-  PMP_CASE(8, 4)
-  PMP_CASE(16, 8)
-  PMP_CASE(8, 16)
-  PMP_CASE(16, 16)
-  PMP_CASE(4, 16)
-  PMP_CASE(16, 4)
+  PMP_TILES(PMP_CASE)
 #undef PMP_CASE
   return hipErrorInvalidValue;
+}
+
+int batch_blocks_per_cu(int g32, int g64) {
+#define PMP_CASE(X, Y) \
+  if (g32 == X && g64 == Y) return occupancy_t<X, Y>();
+  PMP_TILES(PMP_CASE)
+#undef PMP_CASE
+  return 0;
+}
+
+bool batch_tiles_supported(int g32, int g64) {
+#define PMP_CASE(X, Y) \
+  if (g32 == X && g64 == Y) return true;
+  PMP_TILES(PMP_CASE)
+#undef PMP_CASE
+  return false;
 }
 
 // ---------------------------------------------------------------------------

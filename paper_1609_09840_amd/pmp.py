@@ -68,6 +68,7 @@ def _load():
         "pmp_plan_reserve": [vp, u64, i64],
         "pmp_plan_status": [vp, vp],
         "pmp_plan_set_tile": [vp, i32, i32],
+        "pmp_plan_tune": [vp, i32, u32, u64],
         "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
@@ -156,6 +157,9 @@ class Plan:
 
     def set_tile(self, wide: bool, lanes_per_block: int):
         _check(_lib.pmp_plan_set_tile(self.handle, int(wide), lanes_per_block))
+
+    def tune(self, waves_per_cu: int = 0, alpha: int = 0, wave_bytes: int = 0):
+        _check(_lib.pmp_plan_tune(self.handle, waves_per_cu, alpha, wave_bytes))
 
     def status(self, stream=None) -> int:
         return _lib.pmp_plan_status(self.handle, _stream(stream))

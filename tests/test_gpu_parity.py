@@ -203,8 +203,11 @@ def test_bad_offsets_reported():
     plan.close()
 
 
+TILE_PAIRS = [(8, 16), (8, 8), (16, 16), (4, 16), (16, 8), (4, 8)]
+
+
 def test_tiles_agree():
-    """Every lanes-per-block setting gives the same results."""
+    """Every compiled lanes-per-block pair gives the same results."""
     from paper_1609_09840_amd import pmp
 
     rng = np.random.default_rng(91)
@@ -212,12 +215,13 @@ def test_tiles_agree():
         rg = W.from_lengths(rng.integers(0, 300000, size=30), 92, wide, lead=1)
         keys = U.keys_for(wide, 93)
         want = U.oracle_hash(rg, keys, 2)
-        for g in (4, 8, 16):
+        for g32, g64 in TILE_PAIRS:
             plan = pmp.Plan(0)
-            plan.set_tile(wide, g)
-            say(f"case tile G={g} wide={wide}")
+            plan.set_tile(False, g32)
+            plan.set_tile(True, g64)
+            say(f"case tiles ({g32}, {g64}) wide={wide}")
             got = U.gpu_hash(rg, keys, 2, plan=plan)
-            assert U.first_mismatch(got, want) is None, (g, U.first_mismatch(got, want))
+            assert U.first_mismatch(got, want) is None, (g32, g64, U.first_mismatch(got, want))
             plan.close()
 
 
