@@ -121,6 +121,16 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 }
 
 // ---------------------------------------------------------------------------
+// Length classes within a tile of 64 strings: "tiny" strings (at most
+// TINY_GROUPS 16-byte groups of padded string) are hashed one per lane, all
+// their loads in one batch; "medium" strings (the rest of those with at most
+// MEDIUM_BLOCKS blocks, wholly in this wave's share) one per G-lane group;
+// longer strings, or strings cut by the share's ends, by the whole wave.
+constexpr uint32_t TINY_GROUPS = 16;
+constexpr int64_t MEDIUM_BLOCKS = 4;
+constexpr int SHORT_BATCH = 16;  // 16-byte groups per batch of loads in the one-per-lane path
+
+// ---------------------------------------------------------------------------
 // Strings of one block, one per lane. `act` marks lanes with such a string.
 // Each lane walks its string in batches of K 16-byte groups whose loads are
 // all in flight together; the group's keys are wave-uniform scalar loads.
@@ -129,7 +139,7 @@ __device__ void short_strings(const BatchArgs& B, int64_t i, bool act, int64_t o
   using T = Tr<WIDE>;
   constexpr int W = T::W;
   constexpr int WPG = 16 / W;  // words per 16-byte group
-  constexpr int K = 8;         // groups per batch of loads
+  constexpr int K = SHORT_BATCH;  // groups per batch of loads
   const uint8_t* lo = B.buf;
   const uint8_t* hi = B.buf + B.buf_bytes;
   const uint8_t* safe = (const uint8_t*)B.keys;
@@ -543,10 +553,84 @@ __device__ Pos locate(const BatchArgs& B, uint32_t alpha, uint64_t x) {
 }
 
 // All blocks in [ps, pe) of one batch, 64 strings at a time.
+// Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
+// TINY_GROUPS groups), one string per G-lane group: the CPS groups of the
+// wave walk their strings block by block together, each block summed by its
+// group as in block_sum, folded (Sec. 6.2, Algorithm 2) and multiplied into
+// the group's own level-2 sum; no wave-wide reduction is needed. `med`
+// marks lanes whose string (i, o0, len, C1) is medium.
+template <bool WIDE, int G>
+__device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, bool med, int64_t i, int64_t o0, int64_t len,
+                               int64_t C1) {
+  using T = Tr<WIDE>;
+  using Sum = typename T::Sum;
+  constexpr int W = T::W;
+  constexpr int CPS = 64 / G;
+  const int lane = lane_id();
+  const int g = lane / G, j = lane % G;
+  const uint8_t* lo = B.buf;
+  const uint8_t* hi = B.buf + B.buf_bytes;
+  const uint8_t* safe = (const uint8_t*)B.keys;  // 128 W + 4 readable bytes
+  const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
+  const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
+  uint64_t m = __ballot(med);
+  while (m) {
+    // the next CPS medium strings, one per group
+    int own = 64;
+#pragma unroll
+    for (int k = 0; k < CPS; ++k) {
+      const int l = m ? __ffsll((unsigned long long)m) - 1 : 64;
+      if (m) m &= m - 1;
+      if (g == k) own = l;
+    }
+    const bool gact = own < 64;
+    const int src = gact ? own : lane;
+    // shuffles with every lane active (ds_bpermute reads 0 from a disabled
+    // source lane), selections afterwards
+    const int64_t si = __shfl((long long)i, src, 64);
+    const int64_t so = __shfl((long long)o0, src, 64);
+    const int64_t len_s = __shfl((long long)len, src, 64);
+    const int64_t c1_s = __shfl((long long)C1, src, 64);
+    const int64_t sl = gact ? len_s : 0;
+    const int64_t sc = gact ? c1_s : 0;
+    const uint8_t* s = B.buf + so;
+    const uint32_t sh = (uint32_t)((uintptr_t)s & 3u);
+    const uint8_t* a4 = s - sh;
+    const uint32_t nsteps = wave_max((uint32_t)sc);
+    Sum acc2;
+    zero(acc2);
+    Fe res = {0, 0};
+    for (uint32_t c = 0; c < nsteps; ++c) {
+      asm volatile("" ::: "memory");  // keys stay in LDS
+      const bool act = (int64_t)c < sc;
+      const uint8_t* blk = act ? a4 + (int64_t)c * (BLOCK * W) : safe;
+      const int64_t rem = sl - (int64_t)c * (BLOCK * W);
+      const bool inb = !act || inside(blk, BLOCK * W + 4, lo, hi);
+      Sum bs;
+      if (__ballot(!inb)) bs = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
+      else bs = block_sum<WIDE, G, true>(blk, j, sh, lk, act, rem);
+      group_sum<G>(bs);
+      add_word(bs, b1);
+      const Fe z = reduce(bs);
+      if (act) {
+        if (sc == 1) res = z;
+        else mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
+      }
+    }
+    if (sc > 1) {
+      add_word(acc2, b2);
+      res = reduce(acc2);
+    }
+    if (gact && j == 0) store_out<WIDE>(B, si, res);
+  }
+}
+
+// All blocks in [ps, pe) of one batch, 64 strings at a time.
 template <bool WIDE, int G>
 __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk, Pos ps, Pos pe) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
+  constexpr int WPG = 16 / W;
   const int lane = lane_id();
   if (pe.i < ps.i || (pe.i == ps.i && pe.c < ps.c)) {  // only possible when offsets decrease somewhere
     if (lane == 0) __hip_atomic_fetch_or(A.status, STATUS_OFFSETS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -566,23 +650,28 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
       __hip_atomic_fetch_or(A.status, STATUS_OFFSETS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool ok = in && !bad;
     const int64_t len = ok ? o1 - o0 : 0;
-    const int64_t C1 = ((len / W + 1) + BLOCK - 1) / BLOCK;
+    const int64_t nw = len / W + 1;
+    const int64_t C1 = (nw + BLOCK - 1) / BLOCK;
     const int64_t lo_c = (i == ps.i) ? ps.c : 0;
     const int64_t hi_c = (i == pe.i) ? pe.c : C1;
-    const bool shrt = ok && C1 == 1 && lo_c == 0 && hi_c >= 1;
-    const bool lng = ok && C1 > 1 && lo_c < hi_c;
+    const bool whole = ok && lo_c == 0 && hi_c == C1;
+    const bool tiny = whole && (nw + WPG - 1) / WPG <= TINY_GROUPS;
+    const bool med = whole && !tiny && C1 <= MEDIUM_BLOCKS;
+    const bool lng = ok && !tiny && !med && lo_c < hi_c;
 
-    short_strings<WIDE>(B, i, shrt, o0, len);
+    short_strings<WIDE>(B, i, tiny, o0, len);
+    medium_strings<WIDE, G>(B, lk, med, i, o0, len, C1);
 
-    // the long strings, one at a time by the whole wave; their offsets are
-    // read again as scalars rather than kept in vector registers
+    // the long strings, one at a time by the whole wave
     uint64_t m = __ballot(lng);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       const int64_t si = t0 + l;
-      const int64_t so = B.offsets[si];
-      const int64_t sl = B.offsets[si + 1] - so;
+      const int64_t so = (int64_t)uni64(__builtin_amdgcn_readlane((int)(uint32_t)o0, l) |
+                                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(o0 >> 32), l) << 32));
+      const int64_t sl = (int64_t)uni64(__builtin_amdgcn_readlane((int)(uint32_t)len, l) |
+                                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(len >> 32), l) << 32));
       const int64_t sc = ((sl / W + 1) + BLOCK - 1) / BLOCK;
       const int64_t slo = (si == ps.i) ? ps.c : 0;
       const int64_t shi = (si == pe.i) ? pe.c : sc;
