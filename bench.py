@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--g64", type=int, default=0, help="lanes per block, PM+64 (0: default)")
     ap.add_argument("--waves-per-cu", type=int, default=0, help="waves per CU (0: as many as stay resident)")
     ap.add_argument("--alpha", type=int, default=0, help="per-string work weight in bytes (0: default)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -187,6 +190,14 @@ def main():
     from paper_1609_09840_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.randint(0, 255, (args.calibrate_copy,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy, "launches": 5}), flush=True)
+        return
     wl = W.CONFIGS[args.config]()
     keep, batches = setup(wl, dev)
     plan = pmp.Plan(0)

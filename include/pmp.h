@@ -50,7 +50,7 @@ extern "C" {
 #define PMP_E_OFFSETS (-4)     /* offsets decrease or point past buf_bytes   */
 #define PMP_E_HIP (-5)         /* a HIP runtime call failed                  */
 #define PMP_E_NOMEM (-6)       /* workspace allocation failed                */
-#define PMP_E_INTERNAL (-7)    /* device work queue overflow or stall        */
+#define PMP_E_INTERNAL (-7)    /* a tree-node accumulator index fell outside the plan workspace */
 
 /* flags for the hash calls */
 #define PMP_NO_MIX 1u    /* output h mod 2^n without the Sec. 7 mixer        */
@@ -86,8 +86,9 @@ int pmp_check_keys32(const uint32_t* keys);
 int pmp_check_keys64(const uint64_t* keys);
 
 /* ---------------------------------------------------------------------- */
-/* Plans. A plan owns a device workspace (work queue, tree-node scratch,
- * counters, status word) sized for a batch. Calls that share a plan must be
+/* Plans. A plan owns a device workspace (one tree-node accumulator per 128
+ * words of buffer, a status word, a pinned descriptor staging buffer) sized
+ * for a batch. Calls that share a plan must be
  * ordered on one stream. plan == NULL in a hash call selects a default plan
  * private to the (current device, stream) pair, created on first use.
  * Creating or growing a workspace allocates device memory; hash calls on a
@@ -99,7 +100,9 @@ int pmp_plan_destroy(pmp_plan* plan);
 int pmp_plan_reserve(pmp_plan* plan, uint64_t max_buf_bytes, int64_t max_count);
 /* Synchronize `stream`, then return and clear the device-side status of
  * `plan` (NULL: the default plan of the current device and `stream`):
- * PMP_OK, PMP_E_OFFSETS or PMP_E_INTERNAL. */
+ * PMP_OK, PMP_E_OFFSETS or PMP_E_INTERNAL (a consistency check of the
+ * workspace that a correct call never trips). A nonzero status also clears
+ * the workspace so that the plan can be used again. */
 int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream);
 /* Lanes per 128-word block for strings longer than one block, per variant
  * (wide = 0: PM+32, 1: PM+64; 0 = the default, 8 and 16). Compiled pairs:
@@ -132,10 +135,12 @@ int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wav
  *   flags      0, PMP_NO_MIX or PMP_OUT_FIELD
  *   stream     HIP stream the work is queued on; the call returns at once.
  *
- * One persistent kernel launch processes the whole batch: strings of one
- * block are hashed one per lane, longer strings are split into level-2
- * nodes of up to 128 blocks taken from a device work queue, and the levels
- * above 2 are finished by whichever wave completes a node's last child. */
+ * One kernel launch processes the whole batch. The batch is cut into equal
+ * shares of work (bytes plus a per-string weight) by a merge-path split over
+ * the offsets, one share per wave. Strings of at most one block are hashed
+ * one per lane, medium strings one per lane group, long strings a level-2
+ * node (128 blocks) per wave; the levels above 2 are finished by whichever
+ * wave completes a node's last child, through the plan's accumulators. */
 int pmp_hash32(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets,
                int64_t count, const uint32_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream);
 int pmp_hash64(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets,
@@ -158,6 +163,82 @@ typedef struct pmp_batch {
 /* Hash up to two batches (any mix of PM+32 and PM+64) in ONE kernel launch;
  * either pointer may be NULL. Same semantics per batch as pmp_hash32/64. */
 int pmp_hash_mixed(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, pmp_stream_t stream);
+/* Hash any number of batches (a HOST array of nbatch descriptors) in ONE
+ * kernel launch; each batch keeps its own buffer, offsets, keys, output and
+ * flags. With more than two batches the descriptors are uploaded to the
+ * device on `stream` first (through the plan's pinned staging buffer). */
+int pmp_hash_many(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving loop (continuous batching). A server owns `lanes` in-flight
+ * positions, each a HIP stream with its own plan and a device arena of
+ * lane_bytes (plus a pinned host twin). A dispatcher thread takes queued
+ * requests in arrival order and hashes as many as fit one lane in ONE launch
+ * (pmp_hash_many), while earlier launches still run on other lanes.
+ *
+ * A request is a batch of strings of one variant (wide 0: PM+32, 1: PM+64),
+ * hashed with the server's key tables:
+ *   device_resident = 1: buf, offsets, out are device pointers, used in
+ *     place (the caller keeps them alive until the request completes);
+ *   device_resident = 0: they are HOST pointers; payload and offsets are
+ *     copied through the lane arena and the hashes copied back to `out`
+ *     before the request counts as complete. Such a request must fit the
+ *     arena (16-byte rounded payload + offsets + output <= lane_bytes), else
+ *     submit returns PMP_E_NOMEM ("admission by memory"); a request that fits
+ *     waits in the queue until a lane has room.
+ * Latency is measured from submit to completion (results visible in `out`).
+ * Outputs are bit-identical to hashing the request alone with pmp_hash32/64. */
+typedef struct pmp_server pmp_server;
+
+typedef struct pmp_server_config {
+  int device;                     /* HIP device index */
+  int lanes;                      /* in-flight launches, 1..16 */
+  uint64_t lane_bytes;            /* arena per lane for host requests (0: device-resident only) */
+  const uint32_t* d_keys32;       /* device, PM+32 key table (PMP_KEYS entries) */
+  const uint64_t* d_keys64;       /* device, PM+64 key table */
+  int max_requests_per_batch;     /* >= 1 */
+  int64_t max_batch_strings;      /* strings per launch before a lane closes (0: no limit) */
+  uint64_t reserve_bytes;         /* pre-size each lane's plan for this much buffer (0: grow on use) */
+} pmp_server_config;
+
+typedef struct pmp_request {
+  const uint8_t* buf;
+  uint64_t buf_bytes;
+  const int64_t* offsets; /* int64[count + 1], rules as for pmp_hash32 */
+  int64_t count;
+  void* out;              /* as d_out of pmp_hash32/64 */
+  uint32_t flags;
+  uint32_t wide;
+  uint32_t device_resident;
+  uint32_t reserved;
+} pmp_request;
+
+typedef struct pmp_server_report {
+  uint64_t completed, rejected, batches, bytes; /* bytes: payload bytes hashed */
+  double p50_us, p99_us, max_us, mean_us;       /* submit-to-completion latency */
+  double span_us;                               /* first submit to last completion */
+} pmp_server_report;
+
+int pmp_server_create(const pmp_server_config* cfg, pmp_server** out);
+/* Finish every queued request, then free the server. */
+int pmp_server_destroy(pmp_server* server);
+/* Queue a request (any thread). *ticket identifies it for pmp_server_wait. */
+int pmp_server_submit(pmp_server* server, const pmp_request* req, uint64_t* ticket);
+/* Wait for a request: timeout_us < 0 waits for ever. Returns 1 if it is still
+ * pending at the timeout (the ticket stays valid), else its final status
+ * (PMP_OK or a PMP_E_* code) and releases the ticket. Device-side problems
+ * (bad offsets) show in pmp_server_status, not here. */
+int pmp_server_wait(pmp_server* server, uint64_t ticket, int64_t timeout_us);
+/* Latency and throughput over the requests completed since the last reset. */
+int pmp_server_stats(pmp_server* server, pmp_server_report* stats);
+int pmp_server_reset_stats(pmp_server* server);
+/* Load generator: submit reqs[k] at arrival_us[k] microseconds after the
+ * call starts (non-decreasing), wait for all, and write each latency to
+ * latency_us[k] (may be NULL). Returns PMP_OK or the worst request status. */
+int pmp_server_replay(pmp_server* server, const pmp_request* reqs, int64_t n, const double* arrival_us,
+                      double* latency_us);
+/* Device status of every lane's plan, as pmp_plan_status (synchronizes). */
+int pmp_server_status(pmp_server* server);
 
 /* ---------------------------------------------------------------------- */
 /* Plain GPU form, kept as a baseline: one string at a time, one launch per

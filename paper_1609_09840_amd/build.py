@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpmp.so")
-SOURCES = ["pmp_kernels.hip", "pmp_api.cpp"]
+SOURCES = ["pmp_kernels.hip", "pmp_api.cpp", "pmp_server.cpp"]
 HEADERS = ["pmp_device.hpp", "pmp_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -67,7 +67,7 @@ def build(verbose: bool = False) -> str:
     rt = hip_runtime_dir()
     tmp = LIB + ".tmp"
     _run(["g++", "-shared", "-o", tmp, *objs, "-L" + rt, "-l:libamdhip64.so", "-Wl,-rpath," + rt,
-          "-Wl,--no-undefined", "-Wl,-z,now"], verbose)
+          "-pthread", "-Wl,--no-undefined", "-Wl,-z,now"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "pmp.h"
 #include "pmp_internal.h"
@@ -49,6 +50,10 @@ constexpr uint64_t AMAX64 = 0xfffffffffffffff4ull;  // 2^64 + 13 - 24 - 1 = 2^64
 
 }  // namespace
 
+namespace pmp {
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace pmp
+
 struct pmp_plan {
   int device = 0;
   int32_t* status = nullptr;  // device
@@ -59,6 +64,11 @@ struct pmp_plan {
   uint64_t wave_bytes = 8192;  // smallest share of work worth a wave
   int waves_per_cu = 0;        // 0: as many as stay resident
   int cus = 0;
+  // descriptors of calls with more than two batches
+  pmp::BatchArgs* desc_host = nullptr;  // pinned
+  pmp::BatchArgs* desc_dev = nullptr;
+  int desc_cap = 0;
+  hipEvent_t desc_copied = nullptr;  // the last descriptor upload
   std::mutex mu;
 };
 
@@ -147,18 +157,53 @@ int check_batch(const pmp_batch* b) {
   return PMP_OK;
 }
 
-int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStream_t stream) {
-  int r = check_batch(b0);
-  if (r) return r;
-  r = check_batch(b1);
-  if (r) return r;
-  const pmp_batch* list[2];
-  int nb = 0;
-  if (b0 && b0->count > 0) list[nb++] = b0;
-  if (b1 && b1->count > 0) list[nb++] = b1;
+int plan_desc(pmp_plan* p, int n) {
+  if (n <= p->desc_cap) return PMP_OK;
+  hipError_t e;
+  if (p->desc_copied) {
+    e = hipEventSynchronize(p->desc_copied);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  } else {
+    e = hipEventCreateWithFlags(&p->desc_copied, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  }
+  if (p->desc_host) (void)hipHostFree(p->desc_host);
+  if (p->desc_dev) (void)hipFree(p->desc_dev);
+  p->desc_host = nullptr;
+  p->desc_dev = nullptr;
+  p->desc_cap = 0;
+  const int cap = n < 64 ? 64 : 2 * n;
+  e = hipHostMalloc((void**)&p->desc_host, cap * sizeof(pmp::BatchArgs), hipHostMallocDefault);
+  if (e != hipSuccess) return fail(PMP_E_NOMEM, "descriptor staging: %s", hipGetErrorString(e));
+  e = hipMalloc(&p->desc_dev, cap * sizeof(pmp::BatchArgs));
+  if (e != hipSuccess) return fail(PMP_E_NOMEM, "descriptor array: %s", hipGetErrorString(e));
+  p->desc_cap = cap;
+  return PMP_OK;
+}
+
+}  // namespace
+
+namespace pmp {
+
+// Hash n batches in one launch. spans[k] (optional) is offsets[count] -
+// offsets[0] of batch k when the caller knows it.
+int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint64_t* spans, hipStream_t stream) {
+  if (n_in < 0) return fail(PMP_E_INVALID_ARG, "negative batch count");
+  std::vector<const pmp_batch*> list;
+  std::vector<uint64_t> span;
+  list.reserve(n_in);
+  for (int k = 0; k < n_in; ++k) {
+    int r = check_batch(in[k]);
+    if (r) return r;
+    if (in[k] && in[k]->count > 0) {
+      list.push_back(in[k]);
+      span.push_back(spans ? spans[k] : SPAN_UNKNOWN);
+    }
+  }
+  const int nb = (int)list.size();
   if (nb == 0) return PMP_OK;
   if (!plan) {
-    r = default_plan(stream, &plan);
+    int r = default_plan(stream, &plan);
     if (r) return r;
   }
   int dev = 0;
@@ -172,14 +217,16 @@ int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStr
     need += slots_for(list[k]->buf_bytes, (int)list[k]->wide);
     work += list[k]->buf_bytes + (uint64_t)plan->alpha * (uint64_t)list[k]->count;
   }
-  r = plan_slots(plan, need);
+  int r = plan_slots(plan, need);
   if (r) return r;
 
-  pmp::KArgs a;
+  KArgs a;
   std::memset(&a, 0, sizeof a);
+  std::vector<BatchArgs> bv(nb);
   uint64_t base = 0;
   for (int k = 0; k < nb; ++k) {
-    pmp::BatchArgs& B = a.b[k];
+    BatchArgs& B = bv[k];
+    std::memset(&B, 0, sizeof B);
     B.buf = list[k]->buf;
     B.buf_bytes = list[k]->buf_bytes;
     B.offsets = list[k]->offsets;
@@ -190,7 +237,23 @@ int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStr
     B.wide = list[k]->wide;
     B.slots = plan->slots + base;
     B.nslots = slots_for(list[k]->buf_bytes, (int)list[k]->wide);
+    B.span = span[k];
     base += B.nslots;
+  }
+  if (nb <= 2) {
+    for (int k = 0; k < nb; ++k) a.b[k] = bv[k];
+    a.batches = nullptr;
+  } else {
+    r = plan_desc(plan, nb);
+    if (r) return r;
+    // the staging buffer may still feed the previous upload
+    e = hipEventSynchronize(plan->desc_copied);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    std::memcpy(plan->desc_host, bv.data(), nb * sizeof(BatchArgs));
+    e = hipMemcpyAsync(plan->desc_dev, plan->desc_host, nb * sizeof(BatchArgs), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->desc_copied, stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    a.batches = plan->desc_dev;
   }
   a.nbatch = (uint32_t)nb;
   a.alpha = plan->alpha;
@@ -198,7 +261,7 @@ int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStr
 
   // one wave per `wave_bytes` of work, at most what the device keeps resident
   int per_cu = plan->waves_per_cu;
-  if (per_cu <= 0) per_cu = 4 * pmp::batch_blocks_per_cu(plan->g32, plan->g64);
+  if (per_cu <= 0) per_cu = 4 * batch_blocks_per_cu(plan->g32, plan->g64);
   if (per_cu <= 0) per_cu = 8;
   const uint64_t max_waves = (uint64_t)plan->cus * (uint64_t)per_cu;
   uint64_t waves = (work + plan->wave_bytes - 1) / plan->wave_bytes;
@@ -206,9 +269,18 @@ int run_batches(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStr
   if (waves > max_waves) waves = max_waves;
   a.total_waves = (uint32_t)waves;
   const int grid = (int)((waves + 3) / 4);
-  e = pmp::launch_batch(a, grid, plan->g32, plan->g64, stream);
+  e = launch_batch(a, grid, plan->g32, plan->g64, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   return PMP_OK;
+}
+
+}  // namespace pmp
+
+namespace {
+
+int run_two(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStream_t stream) {
+  const pmp_batch* l[2] = {b0, b1};
+  return pmp::run_batches(plan, l, 2, nullptr, stream);
 }
 
 }  // namespace
@@ -282,8 +354,12 @@ int pmp_plan_destroy(pmp_plan* plan) {
     for (auto it = g_default.begin(); it != g_default.end(); ++it)
       if (it->second == plan) return fail(PMP_E_INVALID_ARG, "default plans are owned by the library");
   }
+  (void)hipDeviceSynchronize();
   if (plan->slots) (void)hipFree(plan->slots);
   if (plan->status) (void)hipFree(plan->status);
+  if (plan->desc_host) (void)hipHostFree(plan->desc_host);
+  if (plan->desc_dev) (void)hipFree(plan->desc_dev);
+  if (plan->desc_copied) (void)hipEventDestroy(plan->desc_copied);
   delete plan;
   return PMP_OK;
 }
@@ -342,17 +418,24 @@ int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wav
 int pmp_hash32(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets, int64_t count,
                const uint32_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream) {
   pmp_batch b{d_buf, buf_bytes, d_offsets, count, d_keys, d_out, flags, 0};
-  return run_batches(plan, &b, nullptr, (hipStream_t)stream);
+  return run_two(plan, &b, nullptr, (hipStream_t)stream);
 }
 
 int pmp_hash64(pmp_plan* plan, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets, int64_t count,
                const uint64_t* d_keys, void* d_out, uint32_t flags, pmp_stream_t stream) {
   pmp_batch b{d_buf, buf_bytes, d_offsets, count, d_keys, d_out, flags, 1};
-  return run_batches(plan, &b, nullptr, (hipStream_t)stream);
+  return run_two(plan, &b, nullptr, (hipStream_t)stream);
 }
 
 int pmp_hash_mixed(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, pmp_stream_t stream) {
-  return run_batches(plan, b0, b1, (hipStream_t)stream);
+  return run_two(plan, b0, b1, (hipStream_t)stream);
+}
+
+int pmp_hash_many(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_stream_t stream) {
+  if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(PMP_E_INVALID_ARG, "bad batch array");
+  std::vector<const pmp_batch*> l(nbatch);
+  for (int k = 0; k < nbatch; ++k) l[k] = batches + k;
+  return pmp::run_batches(plan, l.data(), nbatch, nullptr, (hipStream_t)stream);
 }
 
 int pmp_hash_plain(int wide, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* h_offsets, int64_t count,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pmp.h"
+
 namespace pmp {
 
 constexpr uint32_t FLAG_NO_MIX = 1u;
@@ -30,17 +32,25 @@ struct BatchArgs {
   void* out;
   uint32_t flags;
   uint32_t wide;
-  Slot* slots;  // ceil(buf_bytes / (128 W)) + 1 node accumulators
+  Slot* slots;  // ceil(buf_bytes / (128 W)) + 2 node accumulators
   uint64_t nslots;
+  uint64_t span;  // offsets[count] - offsets[0] when the host knows it, else ~0
 };
 
+constexpr uint64_t SPAN_UNKNOWN = ~0ull;
+
 struct KArgs {
-  BatchArgs b[2];
+  BatchArgs b[2];              // up to two batches travel in the arguments...
+  const BatchArgs* batches;    // ...more come as a device array (else null)
   uint32_t nbatch;
   uint32_t alpha;        // per-string work in byte equivalents
   int32_t* status;       // device status word (STATUS_* bits)
-  uint32_t total_waves;  // waves sharing the work (grid * 4 or fewer)
+  uint32_t total_waves;  // waves sharing the work
 };
+
+// host side (pmp_api.cpp)
+int set_error(int code, const char* msg);  // sets the message pmp_last_error returns
+int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint64_t* spans, hipStream_t stream);
 
 // kernels/launchers (pmp_kernels.hip)
 hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s);

@@ -128,7 +128,7 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // longer strings, or strings cut by the share's ends, by the whole wave.
 constexpr uint32_t TINY_GROUPS = 16;
 constexpr int64_t MEDIUM_BLOCKS = 4;
-constexpr int SHORT_BATCH = 16;  // 16-byte groups per batch of loads in the one-per-lane path
+constexpr int SHORT_BATCH = 8;  // 16-byte groups per batch of loads in the one-per-lane path
 
 // ---------------------------------------------------------------------------
 // Strings of one block, one per lane. `act` marks lanes with such a string.
@@ -680,45 +680,87 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
   }
 }
 
+// Work of a batch: alpha per string plus its bytes.
+__device__ __forceinline__ uint64_t batch_work(int64_t count, uint64_t span, const int64_t* offsets,
+                                               uint32_t alpha) {
+  if (count <= 0) return 0;
+  if (span == SPAN_UNKNOWN) {
+    const int64_t d = offsets[count] - offsets[0];
+    span = d > 0 ? (uint64_t)d : 0;
+  }
+  return (uint64_t)alpha * (uint64_t)count + span;
+}
+
+// Work of batch b (lane-varying b). The argument copies of the first two
+// batches are read by selection, never by a dynamic index, which would move
+// the whole argument block to scratch.
+__device__ __forceinline__ uint64_t batch_work_at(const KArgs& A, uint32_t b) {
+  if (b >= A.nbatch) return 0;
+  if (A.batches) {
+    const BatchArgs* B = A.batches + b;
+    return batch_work(B->count, B->span, B->offsets, A.alpha);
+  }
+  const bool one = b != 0;
+  return batch_work(one ? A.b[1].count : A.b[0].count, one ? A.b[1].span : A.b[0].span,
+                    one ? A.b[1].offsets : A.b[0].offsets, A.alpha);
+}
+
 template <int G32, int G64>
 __global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
-  // level-1 and level-2 keys of each batch, as 64-bit words, shared by the
-  // workgroup's four waves
-  __shared__ uint64_t lkeys[2][2 * BLOCK];
-  for (uint32_t b = 0; b < A.nbatch; ++b) {
-    const BatchArgs& B = A.b[b];
-    lkeys[b][threadIdx.x] = B.wide ? ((const uint64_t*)B.keys)[threadIdx.x] : ((const uint32_t*)B.keys)[threadIdx.x];
-  }
-  __syncthreads();
+  // each wave keeps the level-1 and level-2 keys of the batch it works on in
+  // its own LDS region, as 64-bit words
+  __shared__ uint64_t lkeys[4][2 * BLOCK];
+  const int lane = lane_id();
+  uint64_t* lk = lkeys[threadIdx.x / 64];
   const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (w >= A.total_waves) return;
-  uint64_t work[2] = {0, 0};
-  for (uint32_t b = 0; b < A.nbatch; ++b) {
-    const BatchArgs& B = A.b[b];
-    if (B.count > 0) {
-      const int64_t span = B.offsets[B.count] - B.offsets[0];
-      work[b] = (uint64_t)A.alpha * (uint64_t)B.count + (uint64_t)(span > 0 ? span : 0);
-    }
+  const uint32_t nb = A.nbatch;
+  // total work, 64 batches at a time
+  uint64_t total = 0;
+  for (uint32_t base = 0; base < nb; base += 64) {
+    uint64_t t = 0;
+    (void)wave_excl_scan(batch_work_at(A, base + (uint32_t)lane), &t);
+    total += t;
   }
-  const uint64_t total = work[0] + work[1];
   const uint64_t x0 = (uint64_t)(((u128)total * w) / A.total_waves);
   const uint64_t x1 = (uint64_t)(((u128)total * (w + 1)) / A.total_waves);
-  uint64_t bstart = 0;
-  for (uint32_t b = 0; b < A.nbatch; ++b) {
-    const uint64_t bend = bstart + work[b];
-    const uint64_t lo = x0 > bstart ? x0 : bstart;
-    const uint64_t hi = x1 < bend ? x1 : bend;
-    if (lo < hi) {
-      const BatchArgs& B = A.b[b];
-      if (B.wide) {
-        const Pos ps = locate<8>(B, A.alpha, lo - bstart), pe = locate<8>(B, A.alpha, hi - bstart);
-        run_range<true, G64>(A, B, lkeys[b], ps, pe);
-      } else {
-        const Pos ps = locate<4>(B, A.alpha, lo - bstart), pe = locate<4>(B, A.alpha, hi - bstart);
-        run_range<false, G32>(A, B, lkeys[b], ps, pe);
+  // the batches that overlap [x0, x1), in order
+  uint64_t start = 0;
+  for (uint32_t base = 0; base < nb && start < x1; base += 64) {
+    const uint64_t wk = batch_work_at(A, base + (uint32_t)lane);
+    uint64_t ct = 0;
+    const uint64_t p = start + wave_excl_scan(wk, &ct);
+    uint64_t m = __ballot(wk > 0 && p < x1 && p + wk > x0);
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const uint32_t bi = base + (uint32_t)l;
+      const uint64_t bstart = uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)p, l)) |
+                                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(p >> 32), l) << 32));
+      const uint64_t bw = uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wk, l)) |
+                                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(wk >> 32), l) << 32));
+      const BatchArgs B = A.batches ? A.batches[bi] : (bi ? A.b[1] : A.b[0]);
+      const uint64_t lo = x0 > bstart ? x0 - bstart : 0;
+      const uint64_t hi = x1 < bstart + bw ? x1 - bstart : bw;
+      // this batch's keys into the wave's LDS region
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k;
+        lk[e] = B.wide ? ((const uint64_t*)B.keys)[e] : ((const uint32_t*)B.keys)[e];
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (B.wide) {
+        const Pos ps = locate<8>(B, A.alpha, lo), pe = locate<8>(B, A.alpha, hi);
+        run_range<true, G64>(A, B, lk, ps, pe);
+      } else {
+        const Pos ps = locate<4>(B, A.alpha, lo), pe = locate<4>(B, A.alpha, hi);
+        run_range<false, G32>(A, B, lk, ps, pe);
+      }
+      __builtin_amdgcn_wave_barrier();  // all lanes done with the keys before the next batch's
     }
-    bstart = bend;
+    start += ct;
   }
 }
 

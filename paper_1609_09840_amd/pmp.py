@@ -47,6 +47,47 @@ class pmp_batch(ctypes.Structure):
     ]
 
 
+class pmp_server_config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int),
+        ("lanes", ctypes.c_int),
+        ("lane_bytes", ctypes.c_uint64),
+        ("d_keys32", ctypes.c_void_p),
+        ("d_keys64", ctypes.c_void_p),
+        ("max_requests_per_batch", ctypes.c_int),
+        ("max_batch_strings", ctypes.c_int64),
+        ("reserve_bytes", ctypes.c_uint64),
+    ]
+
+
+class pmp_request(ctypes.Structure):
+    _fields_ = [
+        ("buf", ctypes.c_void_p),
+        ("buf_bytes", ctypes.c_uint64),
+        ("offsets", ctypes.c_void_p),
+        ("count", ctypes.c_int64),
+        ("out", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+        ("wide", ctypes.c_uint32),
+        ("device_resident", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class pmp_server_report(ctypes.Structure):
+    _fields_ = [
+        ("completed", ctypes.c_uint64),
+        ("rejected", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64),
+        ("bytes", ctypes.c_uint64),
+        ("p50_us", ctypes.c_double),
+        ("p99_us", ctypes.c_double),
+        ("max_us", ctypes.c_double),
+        ("mean_us", ctypes.c_double),
+        ("span_us", ctypes.c_double),
+    ]
+
+
 def _load():
     if not os.path.exists(_build.LIB):
         raise ImportError(f"libpmp.so is not built ({_build.LIB}); run __graft_entry__.build()")
@@ -72,6 +113,15 @@ def _load():
         "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
+        "pmp_hash_many": [vp, ctypes.POINTER(pmp_batch), i32, vp],
+        "pmp_server_create": [ctypes.POINTER(pmp_server_config), ctypes.POINTER(vp)],
+        "pmp_server_destroy": [vp],
+        "pmp_server_submit": [vp, ctypes.POINTER(pmp_request), ctypes.POINTER(u64)],
+        "pmp_server_wait": [vp, u64, i64],
+        "pmp_server_stats": [vp, ctypes.POINTER(pmp_server_report)],
+        "pmp_server_reset_stats": [vp],
+        "pmp_server_replay": [vp, ctypes.POINTER(pmp_request), i64, vp, vp],
+        "pmp_server_status": [vp],
         "pmp_hash_plain": [i32, vp, u64, vp, i64, vp, vp, u32, vp, u64, vp],
         "pmp_debug_fold": [i32, vp, vp, vp, vp, i64, vp],
     }
@@ -247,6 +297,97 @@ def pmp_hash_mixed(b0: pmp_batch | None, b1: pmp_batch | None, stream=None, plan
     p0 = ctypes.byref(b0) if b0 is not None else None
     p1 = ctypes.byref(b1) if b1 is not None else None
     _check(_lib.pmp_hash_mixed(_plan_ptr(plan), p0, p1, _stream(stream)))
+
+
+def pmp_hash_many(batches, stream=None, plan: Plan | None = None):
+    """Any number of batches (list of pmp_batch) in one kernel launch."""
+    arr = (pmp_batch * max(1, len(batches)))(*batches)
+    _check(_lib.pmp_hash_many(_plan_ptr(plan), arr, len(batches), _stream(stream)))
+
+
+# -- serving ---------------------------------------------------------------
+def _host_ptr(a: np.ndarray, name: str):
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"{name} must be C-contiguous")
+    return a.ctypes.data if a.size else 0
+
+
+class Server:
+    """Continuous-batching server (pmp_server_*). Requests are hashed with the
+    key tables given here (device tensors, uint32[1032] and uint64[1032])."""
+
+    def __init__(self, keys32, keys64, device: int = 0, lanes: int = 2, lane_bytes: int = 64 << 20,
+                 max_requests_per_batch: int = 256, max_batch_strings: int = 0, reserve_bytes: int = 0):
+        self._keys = (keys32, keys64)  # keep the tables alive
+        cfg = pmp_server_config(device=device, lanes=lanes, lane_bytes=lane_bytes,
+                                d_keys32=_dev_ptr(keys32, "keys32"), d_keys64=_dev_ptr(keys64, "keys64"),
+                                max_requests_per_batch=max_requests_per_batch,
+                                max_batch_strings=max_batch_strings, reserve_bytes=reserve_bytes)
+        h = ctypes.c_void_p()
+        _check(_lib.pmp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}
+
+    @staticmethod
+    def request(wide: bool, buf, offsets, out, flags: int = 0) -> pmp_request:
+        """A request over numpy arrays (host: staged through a lane arena) or
+        device tensors (hashed in place). The arrays must outlive the request."""
+        import torch
+
+        if isinstance(buf, torch.Tensor):
+            return pmp_request(buf=buf.data_ptr() if buf.numel() else 0, buf_bytes=buf.numel(),
+                               offsets=offsets.data_ptr(), count=offsets.numel() - 1, out=out.data_ptr(),
+                               flags=flags, wide=int(wide), device_resident=1)
+        return pmp_request(buf=_host_ptr(buf, "buf"), buf_bytes=buf.size, offsets=_host_ptr(offsets, "offsets"),
+                           count=len(offsets) - 1, out=_host_ptr(out, "out"), flags=flags, wide=int(wide),
+                           device_resident=0)
+
+    def submit(self, req: pmp_request, keep=None) -> int:
+        t = ctypes.c_uint64()
+        _check(_lib.pmp_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = keep
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        rc = _lib.pmp_server_wait(self.handle, ticket, timeout_us)
+        if rc == 1:
+            return rc
+        self._live.pop(ticket, None)
+        return _check(rc)
+
+    def replay(self, reqs, arrival_us: np.ndarray) -> np.ndarray:
+        """Submit reqs[k] at arrival_us[k] (microseconds from the start), wait
+        for all; returns each request's latency in microseconds."""
+        n = len(reqs)
+        arr = (pmp_request * max(1, n))(*reqs)
+        at = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        lat = np.zeros(n, dtype=np.float64)
+        _check(_lib.pmp_server_replay(self.handle, arr, n, at.ctypes.data_as(ctypes.c_void_p),
+                                      lat.ctypes.data_as(ctypes.c_void_p)))
+        return lat
+
+    def stats(self) -> dict:
+        r = pmp_server_report()
+        _check(_lib.pmp_server_stats(self.handle, ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in pmp_server_report._fields_}
+
+    def reset_stats(self):
+        _check(_lib.pmp_server_reset_stats(self.handle))
+
+    def status(self) -> int:
+        return _lib.pmp_server_status(self.handle)
+
+    def close(self):
+        if self.handle:
+            _check(_lib.pmp_server_destroy(self.handle))
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pmp_hash_plain(wide: bool, buf, h_offsets: np.ndarray, keys, out, flags: int, scratch, stream=None):

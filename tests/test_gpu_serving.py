@@ -1,0 +1,190 @@
+"""Many batches in one launch, and the serving loop: every output equals the
+oracle's and the output of the same request hashed alone, bit for bit.
+
+Requests follow the serving workload: 1..4096 strings per request, lengths
+log-uniform in [16 B, 64 KiB], variant drawn per request (scaled down in
+count where a test only needs a mix)."""
+from __future__ import annotations
+
+import threading
+
+import numpy as np
+import pytest
+
+import gpu_util as U
+from paper_1609_09840_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_of(rg, flags=0):
+    return U.oracle_hash(rg, U.keys_for(rg.wide, W.KEY_SEED64 if rg.wide else W.KEY_SEED32), flags)
+
+
+def out_dtype(wide, flags):
+    import torch
+
+    if flags & 2:
+        return torch.uint64
+    return torch.uint64 if wide else torch.uint32
+
+
+def out_len(rg, flags):
+    return rg.count * (2 if (rg.wide and flags & 2) else 1)
+
+
+def small_request(rng, data_seed, max_count=256):
+    count = int(rng.integers(1, max_count + 1))
+    lengths = np.rint(np.exp(rng.uniform(np.log(16.0), np.log(65536.0), size=count))).astype(np.int64)
+    return W.from_lengths(lengths, data_seed, bool(rng.random() < 0.5))
+
+
+def test_hash_many_vs_oracle():
+    """Seven batches (both variants, all output modes, an empty one, offsets
+    that do not start at 0) in one launch, then three in a second launch on
+    the same plan."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(501)
+    specs = []
+    for k in range(7):
+        wide = bool(k % 2)
+        flags = k % 3
+        lengths = rng.integers(0, 40000, size=int(rng.integers(1, 300)))
+        if k == 4:
+            lengths = np.zeros(0, np.int64)
+        specs.append((W.from_lengths(lengths, 510 + k, wide, lead=k), flags))
+    plan = pmp.Plan(0)
+    k32 = U.to_dev_keys(U.keys_for(False, W.KEY_SEED32))
+    k64 = U.to_dev_keys(U.keys_for(True, W.KEY_SEED64))
+    for rounds in ([0, 1, 2, 3, 4, 5, 6], [6, 3, 0]):
+        say(f"case hash_many batches={rounds}")
+        keep, batches = [], []
+        for k in rounds:
+            rg, flags = specs[k]
+            buf, off = U.to_dev(rg)
+            out = torch.zeros(out_len(rg, flags), dtype=out_dtype(rg.wide, flags), device=U.dev())
+            keep.append((rg, flags, buf, off, out))
+            batches.append(pmp.make_batch(rg.wide, buf, off, k64 if rg.wide else k32, out, flags))
+        pmp.pmp_hash_many(batches, plan=plan)
+        torch.cuda.synchronize()
+        assert plan.status() == pmp.PMP_OK
+        for rg, flags, buf, off, out in keep:
+            got = U.as_u64(out.cpu().numpy())
+            want = oracle_of(rg, flags)
+            assert U.first_mismatch(got, want) is None, U.first_mismatch(got, want)
+    plan.close()
+
+
+def _server(lanes=2, lane_bytes=64 << 20, **kw):
+    from paper_1609_09840_amd import pmp
+
+    k32 = U.to_dev_keys(U.keys_for(False, W.KEY_SEED32))
+    k64 = U.to_dev_keys(U.keys_for(True, W.KEY_SEED64))
+    return pmp.Server(k32, k64, device=0, lanes=lanes, lane_bytes=lane_bytes, **kw)
+
+
+def test_server_device_requests_alone_equals_mix():
+    """Poisson arrivals fast enough to overlap; each request's output is the
+    oracle's and the same as that request hashed alone with pmp_hash32/64."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(601)
+    reqs, keep = [], []
+    for k in range(24):
+        rg = W.c5_request(rng, 610 + k) if k % 3 == 0 else small_request(rng, 610 + k)
+        buf, off = U.to_dev(rg)
+        out = torch.zeros(rg.count, dtype=out_dtype(rg.wide, 0), device=U.dev())
+        keep.append((rg, buf, off, out))
+        reqs.append(pmp.Server.request(rg.wide, buf, off, out))
+    arrivals = np.cumsum(rng.exponential(300.0, size=len(reqs)))  # mean gap 300 us
+    say(f"case server device-resident: {len(reqs)} requests, {sum(k[0].nbytes for k in keep)} bytes")
+    srv = _server(lanes=3)
+    lat = srv.replay(reqs, arrivals)
+    assert srv.status() == pmp.PMP_OK
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["completed"] == len(reqs) and np.all(lat > 0)
+    srv.close()
+    for rg, buf, off, out in keep:
+        got = U.as_u64(out.cpu().numpy())
+        alone = U.gpu_hash(rg, U.keys_for(rg.wide, W.KEY_SEED64 if rg.wide else W.KEY_SEED32), 0, buf=buf, off=off)
+        want = oracle_of(rg)
+        assert U.first_mismatch(got, alone) is None, ("mix vs alone", U.first_mismatch(got, alone))
+        assert U.first_mismatch(got, want) is None, ("mix vs oracle", U.first_mismatch(got, want))
+
+
+def test_server_host_requests_and_admission():
+    """Host requests are staged through the lane arenas; one larger than an
+    arena is refused at submit; the rest complete with the oracle's values."""
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(701)
+    lane_bytes = 4 << 20
+    srv = _server(lanes=2, lane_bytes=lane_bytes, max_requests_per_batch=8)
+    big = W.from_lengths([lane_bytes], 702, False)
+    big_out = np.zeros(1, np.uint32)
+    say("case server admission: request larger than the arena")
+    with pytest.raises(pmp.PmpError) as ei:
+        srv.submit(pmp.Server.request(False, big.buf, big.offsets, big_out))
+    assert ei.value.code == pmp.PMP_E_NOMEM
+    reqs, keep = [], []
+    for k in range(40):
+        rg = small_request(rng, 710 + k, max_count=64)
+        flags = int(rng.integers(0, 3))
+        n = out_len(rg, flags)
+        out = np.zeros(n, np.uint64 if (rg.wide or flags & 2) else np.uint32)
+        keep.append((rg, flags, out))
+        reqs.append(pmp.Server.request(rg.wide, rg.buf, rg.offsets, out, flags))
+    say(f"case server host requests: {len(reqs)} requests")
+    lat = srv.replay(reqs, np.cumsum(rng.exponential(100.0, size=len(reqs))))
+    assert srv.status() == pmp.PMP_OK
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["completed"] == len(reqs) and st["rejected"] == 1 and np.all(lat > 0)
+    srv.close()
+    for rg, flags, out in keep:
+        want = oracle_of(rg, flags)
+        assert U.first_mismatch(U.as_u64(out), want) is None, U.first_mismatch(U.as_u64(out), want)
+
+
+def test_server_submit_from_threads():
+    """Four host threads submit and wait concurrently on one server."""
+    from paper_1609_09840_amd import pmp
+
+    srv = _server(lanes=2, lane_bytes=16 << 20)
+    results, errors = {}, []
+
+    def worker(t):
+        try:
+            rng = np.random.default_rng(800 + t)
+            for k in range(10):
+                rg = small_request(rng, 8000 + 100 * t + k, max_count=32)
+                out = np.zeros(rg.count, np.uint64 if rg.wide else np.uint32)
+                tk = srv.submit(pmp.Server.request(rg.wide, rg.buf, rg.offsets, out), keep=(rg, out))
+                assert srv.wait(tk) == pmp.PMP_OK
+                results[(t, k)] = (rg, out)
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    say("case server threads: 4 x 10 requests")
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=120)
+    assert not errors, errors
+    assert srv.status() == pmp.PMP_OK
+    srv.close()
+    assert len(results) == 40
+    for rg, out in results.values():
+        want = oracle_of(rg)
+        assert U.first_mismatch(U.as_u64(out), want) is None
