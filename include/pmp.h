@@ -169,6 +169,35 @@ int pmp_hash_mixed(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, pmp
  * device on `stream` first (through the plan's pinned staging buffer). */
 int pmp_hash_many(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_stream_t stream);
 
+/* Captured launches (hipGraph). pmp_graph_create captures the launch that
+ * pmp_hash_many(plan, batches, nbatch, .) would make into a graph, with the
+ * plan's current tiles and launch shape; pmp_graph_launch replays it on any
+ * stream at the cost of one graph launch. The graph keeps the batch
+ * descriptors (pointers, counts, flags) fixed; the CONTENTS of the buffers,
+ * offsets, keys and outputs are read at each replay, so new data in the same
+ * buffers is hashed by the next replay. The plan must not be used by other
+ * calls while a replay runs, and must outlive the graph. Creation allocates
+ * (workspace, descriptors); replays do not. */
+typedef struct pmp_graph pmp_graph;
+int pmp_graph_create(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_graph** graph_out);
+int pmp_graph_launch(pmp_graph* graph, pmp_stream_t stream);
+int pmp_graph_destroy(pmp_graph* graph);
+
+/* Autotuner: times pmp_hash_many(plan, batches, nbatch, stream) over every
+ * compiled lanes-per-block pair and per-string weight alpha in {32, 64, 128},
+ * then over launch widths of 4, 12 and 16 waves per CU on the best of those,
+ * leaves the fastest setting in the plan and reports it in *best (may be
+ * NULL). The outputs are written by every timed launch (same values). The
+ * stream is synchronized. */
+typedef struct pmp_tuning {
+  int32_t g32, g64;     /* lanes per block, PM+32 / PM+64 */
+  uint32_t alpha;       /* per-string work weight, bytes */
+  int32_t waves_per_cu; /* 0: as many as stay resident */
+  float ms;             /* mean launch time of the chosen setting */
+} pmp_tuning;
+int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_stream_t stream,
+                      pmp_tuning* best);
+
 /* ---------------------------------------------------------------------- */
 /* Serving loop (continuous batching). A server owns `lanes` in-flight
  * positions, each a HIP stream with its own plan and a device arena of

@@ -183,35 +183,26 @@ int plan_desc(pmp_plan* p, int n) {
 
 }  // namespace
 
-namespace pmp {
+namespace {
 
-// Hash n batches in one launch. spans[k] (optional) is offsets[count] -
-// offsets[0] of batch k when the caller knows it.
-int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint64_t* spans, hipStream_t stream) {
-  if (n_in < 0) return fail(PMP_E_INVALID_ARG, "negative batch count");
-  std::vector<const pmp_batch*> list;
-  std::vector<uint64_t> span;
-  list.reserve(n_in);
-  for (int k = 0; k < n_in; ++k) {
-    int r = check_batch(in[k]);
-    if (r) return r;
-    if (in[k] && in[k]->count > 0) {
-      list.push_back(in[k]);
-      span.push_back(spans ? spans[k] : SPAN_UNKNOWN);
-    }
-  }
+// A launch ready to go: kernel arguments (descriptor pointer still unset
+// for more than two batches), grid and the batch descriptors.
+struct Prepared {
+  pmp::KArgs a;
+  int grid = 0;
+  int nb = 0;
+  std::vector<pmp::BatchArgs> bv;
+};
+
+// Check the batches, size the plan workspace, fill the descriptors and pick
+// the grid. Called with plan->mu held.
+int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, const std::vector<uint64_t>& span,
+            Prepared& P) {
+  using namespace pmp;
   const int nb = (int)list.size();
+  P.nb = nb;
+  std::memset(&P.a, 0, sizeof P.a);
   if (nb == 0) return PMP_OK;
-  if (!plan) {
-    int r = default_plan(stream, &plan);
-    if (r) return r;
-  }
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (dev != plan->device) return fail(PMP_E_INVALID_ARG, "plan belongs to device %d, current is %d", plan->device, dev);
-
-  std::lock_guard<std::mutex> lk(plan->mu);
   uint64_t need = 0, work = 0;
   for (int k = 0; k < nb; ++k) {
     need += slots_for(list[k]->buf_bytes, (int)list[k]->wide);
@@ -219,13 +210,10 @@ int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint
   }
   int r = plan_slots(plan, need);
   if (r) return r;
-
-  KArgs a;
-  std::memset(&a, 0, sizeof a);
-  std::vector<BatchArgs> bv(nb);
+  P.bv.assign(nb, BatchArgs{});
   uint64_t base = 0;
   for (int k = 0; k < nb; ++k) {
-    BatchArgs& B = bv[k];
+    BatchArgs& B = P.bv[k];
     std::memset(&B, 0, sizeof B);
     B.buf = list[k]->buf;
     B.buf_bytes = list[k]->buf_bytes;
@@ -240,25 +228,12 @@ int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint
     B.span = span[k];
     base += B.nslots;
   }
-  if (nb <= 2) {
-    for (int k = 0; k < nb; ++k) a.b[k] = bv[k];
-    a.batches = nullptr;
-  } else {
-    r = plan_desc(plan, nb);
-    if (r) return r;
-    // the staging buffer may still feed the previous upload
-    e = hipEventSynchronize(plan->desc_copied);
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    std::memcpy(plan->desc_host, bv.data(), nb * sizeof(BatchArgs));
-    e = hipMemcpyAsync(plan->desc_dev, plan->desc_host, nb * sizeof(BatchArgs), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipEventRecord(plan->desc_copied, stream);
-    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-    a.batches = plan->desc_dev;
-  }
-  a.nbatch = (uint32_t)nb;
-  a.alpha = plan->alpha;
-  a.status = plan->status;
-
+  if (nb <= 2)
+    for (int k = 0; k < nb; ++k) P.a.b[k] = P.bv[k];
+  P.a.batches = nullptr;
+  P.a.nbatch = (uint32_t)nb;
+  P.a.alpha = plan->alpha;
+  P.a.status = plan->status;
   // one wave per `wave_bytes` of work, at most what the device keeps resident
   int per_cu = plan->waves_per_cu;
   if (per_cu <= 0) per_cu = 4 * batch_blocks_per_cu(plan->g32, plan->g64);
@@ -267,14 +242,84 @@ int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint
   uint64_t waves = (work + plan->wave_bytes - 1) / plan->wave_bytes;
   if (waves < 1) waves = 1;
   if (waves > max_waves) waves = max_waves;
-  a.total_waves = (uint32_t)waves;
-  const int grid = (int)((waves + 3) / 4);
-  e = launch_batch(a, grid, plan->g32, plan->g64, stream);
+  P.a.total_waves = (uint32_t)waves;
+  P.grid = (int)((waves + 3) / 4);
+  return PMP_OK;
+}
+
+// Validate and keep the non-empty batches.
+int collect(const pmp_batch* const* in, int n_in, const uint64_t* spans, std::vector<const pmp_batch*>& list,
+            std::vector<uint64_t>& span) {
+  if (n_in < 0) return fail(PMP_E_INVALID_ARG, "negative batch count");
+  list.reserve(n_in);
+  for (int k = 0; k < n_in; ++k) {
+    int r = check_batch(in[k]);
+    if (r) return r;
+    if (in[k] && in[k]->count > 0) {
+      list.push_back(in[k]);
+      span.push_back(spans ? spans[k] : pmp::SPAN_UNKNOWN);
+    }
+  }
+  return PMP_OK;
+}
+
+int current_plan(pmp_plan** plan, hipStream_t stream) {
+  if (!*plan) {
+    int r = default_plan(stream, plan);
+    if (r) return r;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != (*plan)->device)
+    return fail(PMP_E_INVALID_ARG, "plan belongs to device %d, current is %d", (*plan)->device, dev);
+  return PMP_OK;
+}
+
+}  // namespace
+
+namespace pmp {
+
+// Hash n batches in one launch. spans[k] (optional) is offsets[count] -
+// offsets[0] of batch k when the caller knows it.
+int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint64_t* spans, hipStream_t stream) {
+  std::vector<const pmp_batch*> list;
+  std::vector<uint64_t> span;
+  int r = collect(in, n_in, spans, list, span);
+  if (r || list.empty()) return r;
+  r = current_plan(&plan, stream);
+  if (r) return r;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  Prepared P;
+  r = prepare(plan, list, span, P);
+  if (r) return r;
+  hipError_t e;
+  if (P.nb > 2) {
+    r = plan_desc(plan, P.nb);
+    if (r) return r;
+    // the staging buffer may still feed the previous upload
+    e = hipEventSynchronize(plan->desc_copied);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    std::memcpy(plan->desc_host, P.bv.data(), P.nb * sizeof(BatchArgs));
+    e = hipMemcpyAsync(plan->desc_dev, plan->desc_host, P.nb * sizeof(BatchArgs), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->desc_copied, stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    P.a.batches = plan->desc_dev;
+  }
+  e = launch_batch(P.a, P.grid, plan->g32, plan->g64, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   return PMP_OK;
 }
 
 }  // namespace pmp
+
+// A captured launch (hipGraph) over fixed batch descriptors.
+struct pmp_graph {
+  pmp_plan* plan = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  pmp::BatchArgs* desc = nullptr;  // device, owned (more than two batches)
+};
 
 namespace {
 
@@ -436,6 +481,147 @@ int pmp_hash_many(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_
   std::vector<const pmp_batch*> l(nbatch);
   for (int k = 0; k < nbatch; ++k) l[k] = batches + k;
   return pmp::run_batches(plan, l.data(), nbatch, nullptr, (hipStream_t)stream);
+}
+
+int pmp_graph_create(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_graph** out) {
+  if (!plan || !out || nbatch < 0 || (nbatch > 0 && !batches)) return fail(PMP_E_INVALID_ARG, "bad arguments");
+  *out = nullptr;
+  std::vector<const pmp_batch*> in(nbatch);
+  for (int k = 0; k < nbatch; ++k) in[k] = batches + k;
+  std::vector<const pmp_batch*> list;
+  std::vector<uint64_t> span;
+  int r = collect(in.data(), nbatch, nullptr, list, span);
+  if (r) return r;
+  r = current_plan(&plan, nullptr);
+  if (r) return r;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  Prepared P;
+  r = prepare(plan, list, span, P);  // grows the workspace now, outside the capture
+  if (r) return r;
+  pmp_graph* g = new pmp_graph();
+  g->plan = plan;
+  hipError_t e = hipSuccess;
+  hipStream_t cs = nullptr;
+  auto bail = [&](int code, const char* what) {
+    if (cs) (void)hipStreamDestroy(cs);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->desc) (void)hipFree(g->desc);
+    delete g;
+    return code == PMP_E_HIP ? hip_fail(e, what) : fail(code, "%s: %s", what, hipGetErrorString(e));
+  };
+  if (P.nb > 2) {
+    e = hipMalloc(&g->desc, P.nb * sizeof(pmp::BatchArgs));
+    if (e != hipSuccess) return bail(PMP_E_NOMEM, "graph descriptors");
+    e = hipMemcpy(g->desc, P.bv.data(), P.nb * sizeof(pmp::BatchArgs), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(PMP_E_HIP, "graph descriptor upload");
+    P.a.batches = g->desc;
+  }
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(PMP_E_HIP, "capture stream");
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bail(PMP_E_HIP, "hipStreamBeginCapture");
+  hipError_t le = P.nb ? pmp::launch_batch(P.a, P.grid, plan->g32, plan->g64, cs) : hipSuccess;
+  e = hipStreamEndCapture(cs, &g->graph);
+  if (le != hipSuccess) {
+    e = le;
+    return bail(PMP_E_HIP, "captured launch");
+  }
+  if (e != hipSuccess) return bail(PMP_E_HIP, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(PMP_E_HIP, "hipGraphInstantiate");
+  (void)hipStreamDestroy(cs);
+  *out = g;
+  return PMP_OK;
+}
+
+int pmp_graph_launch(pmp_graph* graph, pmp_stream_t stream) {
+  if (!graph) return fail(PMP_E_INVALID_ARG, "graph is NULL");
+  hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return PMP_OK;
+}
+
+int pmp_graph_destroy(pmp_graph* graph) {
+  if (!graph) return PMP_OK;
+  (void)hipDeviceSynchronize();  // replays may still read the descriptors
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  if (graph->desc) (void)hipFree(graph->desc);
+  delete graph;
+  return PMP_OK;
+}
+
+int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_stream_t stream,
+                      pmp_tuning* best) {
+  if (!plan || nbatch < 0 || (nbatch > 0 && !batches)) return fail(PMP_E_INVALID_ARG, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  // time one configuration: one warm launch, then the mean of `reps`
+  auto measure = [&](float* ms) -> int {
+    int r = pmp_hash_many(plan, batches, nbatch, stream);
+    if (r) return r;
+    const int reps = 3;
+    hipError_t x = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && !r; ++k) r = pmp_hash_many(plan, batches, nbatch, stream);
+    if (r) return r;
+    if (x == hipSuccess) x = hipEventRecord(e1, s);
+    if (x == hipSuccess) x = hipEventSynchronize(e1);
+    if (x == hipSuccess) x = hipEventElapsedTime(ms, e0, e1);
+    if (x != hipSuccess) return hip_fail(x, "autotune timing");
+    *ms /= reps;
+    return PMP_OK;
+  };
+  pmp_tuning cur{plan->g32, plan->g64, plan->alpha, plan->waves_per_cu, 0.f};
+  pmp_tuning top = cur;
+  top.ms = 1e30f;
+  int pairs[16][2];
+  const int np = pmp::batch_tile_pairs(pairs, 16);
+  const uint32_t alphas[] = {32, 64, 128};
+  int r = PMP_OK;
+  for (int t = 0; t < np && !r; ++t)
+    for (uint32_t al : alphas) {
+      {
+        std::lock_guard<std::mutex> lk(plan->mu);
+        plan->g32 = pairs[t][0];
+        plan->g64 = pairs[t][1];
+        plan->alpha = al;
+        plan->waves_per_cu = 0;
+      }
+      float ms = 0;
+      r = measure(&ms);
+      if (r) break;
+      if (ms < top.ms) top = pmp_tuning{pairs[t][0], pairs[t][1], al, 0, ms};
+    }
+  if (!r) {  // then the launch width, on the best tiles
+    const int wpcs[] = {4, 12, 16};
+    for (int w : wpcs) {
+      {
+        std::lock_guard<std::mutex> lk(plan->mu);
+        plan->g32 = top.g32;
+        plan->g64 = top.g64;
+        plan->alpha = top.alpha;
+        plan->waves_per_cu = w;
+      }
+      float ms = 0;
+      r = measure(&ms);
+      if (r) break;
+      if (ms < top.ms) top = pmp_tuning{top.g32, top.g64, top.alpha, w, ms};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(plan->mu);
+  const pmp_tuning keep = r ? cur : top;
+  plan->g32 = keep.g32;
+  plan->g64 = keep.g64;
+  plan->alpha = keep.alpha;
+  plan->waves_per_cu = keep.waves_per_cu;
+  if (best) *best = keep;
+  return r;
 }
 
 int pmp_hash_plain(int wide, const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* h_offsets, int64_t count,

@@ -56,6 +56,7 @@ int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint
 hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s);
 int batch_blocks_per_cu(int g32, int g64);       // resident 256-thread blocks per CU
 bool batch_tiles_supported(int g32, int g64);    // compiled lanes-per-block pairs
+int batch_tile_pairs(int (*pairs)[2], int max);  // list them; returns how many
 hipError_t launch_plain_string(int wide, const uint8_t* buf, uint64_t buf_bytes, int64_t o0, int64_t len,
                                const void* keys, void* out, int64_t index, uint32_t flags, uint4* scratch,
                                uint64_t scratch_slots, hipStream_t s);

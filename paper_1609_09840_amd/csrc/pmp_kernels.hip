@@ -795,6 +795,19 @@ int batch_blocks_per_cu(int g32, int g64) {
   return 0;
 }
 
+int batch_tile_pairs(int (*pairs)[2], int max) {
+  int n = 0;
+#define PMP_CASE(X, Y)  \
+  if (n < max) {        \
+    pairs[n][0] = X;    \
+    pairs[n][1] = Y;    \
+  }                     \
+  ++n;
+  PMP_TILES(PMP_CASE)
+#undef PMP_CASE
+  return n < max ? n : max;
+}
+
 bool batch_tiles_supported(int g32, int g64) {
 #define PMP_CASE(X, Y) \
   if (g32 == X && g64 == Y) return true;

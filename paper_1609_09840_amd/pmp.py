@@ -74,6 +74,16 @@ class pmp_request(ctypes.Structure):
     ]
 
 
+class pmp_tuning(ctypes.Structure):
+    _fields_ = [
+        ("g32", ctypes.c_int32),
+        ("g64", ctypes.c_int32),
+        ("alpha", ctypes.c_uint32),
+        ("waves_per_cu", ctypes.c_int32),
+        ("ms", ctypes.c_float),
+    ]
+
+
 class pmp_server_report(ctypes.Structure):
     _fields_ = [
         ("completed", ctypes.c_uint64),
@@ -114,6 +124,10 @@ def _load():
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
         "pmp_hash_many": [vp, ctypes.POINTER(pmp_batch), i32, vp],
+        "pmp_graph_create": [vp, ctypes.POINTER(pmp_batch), i32, ctypes.POINTER(vp)],
+        "pmp_graph_launch": [vp, vp],
+        "pmp_graph_destroy": [vp],
+        "pmp_plan_autotune": [vp, ctypes.POINTER(pmp_batch), i32, vp, ctypes.POINTER(pmp_tuning)],
         "pmp_server_create": [ctypes.POINTER(pmp_server_config), ctypes.POINTER(vp)],
         "pmp_server_destroy": [vp],
         "pmp_server_submit": [vp, ctypes.POINTER(pmp_request), ctypes.POINTER(u64)],
@@ -303,6 +317,40 @@ def pmp_hash_many(batches, stream=None, plan: Plan | None = None):
     """Any number of batches (list of pmp_batch) in one kernel launch."""
     arr = (pmp_batch * max(1, len(batches)))(*batches)
     _check(_lib.pmp_hash_many(_plan_ptr(plan), arr, len(batches), _stream(stream)))
+
+
+class Graph:
+    """A captured pmp_hash_many launch (pmp_graph_*), replayed by launch()."""
+
+    def __init__(self, plan: Plan, batches):
+        self._keep = (plan, list(batches))
+        arr = (pmp_batch * max(1, len(batches)))(*batches)
+        h = ctypes.c_void_p()
+        _check(_lib.pmp_graph_create(plan.handle, arr, len(batches), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(_lib.pmp_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            _check(_lib.pmp_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pmp_plan_autotune(plan: Plan, batches, stream=None) -> dict:
+    """Time the compiled tile pairs and launch shapes on these batches and
+    keep the fastest in the plan; returns the chosen setting."""
+    arr = (pmp_batch * max(1, len(batches)))(*batches)
+    t = pmp_tuning()
+    _check(_lib.pmp_plan_autotune(plan.handle, arr, len(batches), _stream(stream), ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in pmp_tuning._fields_}
 
 
 # -- serving ---------------------------------------------------------------

@@ -188,3 +188,82 @@ def test_server_submit_from_threads():
     for rg, out in results.values():
         want = oracle_of(rg)
         assert U.first_mismatch(U.as_u64(out), want) is None
+
+
+def _batches_for(specs, k32, k64):
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    keep, batches = [], []
+    for rg, flags in specs:
+        buf, off = U.to_dev(rg)
+        out = torch.zeros(out_len(rg, flags), dtype=out_dtype(rg.wide, flags), device=U.dev())
+        keep.append((rg, flags, buf, off, out))
+        batches.append(pmp.make_batch(rg.wide, buf, off, k64 if rg.wide else k32, out, flags))
+    return keep, batches
+
+
+@pytest.mark.parametrize("nb", [2, 5])
+def test_graph_replays(nb):
+    """A captured launch replayed several times, with eager work and new data
+    in the same buffers between replays; every replay matches the oracle."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(900 + nb)
+    specs = []
+    for k in range(nb):
+        lengths = rng.integers(0, 70000, size=int(rng.integers(1, 200)))
+        specs.append((W.from_lengths(lengths, 910 + k, bool(k % 2)), k % 3))
+    k32 = U.to_dev_keys(U.keys_for(False, W.KEY_SEED32))
+    k64 = U.to_dev_keys(U.keys_for(True, W.KEY_SEED64))
+    keep, batches = _batches_for(specs, k32, k64)
+    plan = pmp.Plan(0)
+    say(f"case graph nb={nb}")
+    g = pmp.Graph(plan, batches)
+    stream = torch.cuda.current_stream()
+    for rep in range(3):
+        if rep:  # new bytes in the same buffers, and some eager work between replays
+            for rg, flags, buf, off, out in keep:
+                rg.buf[:] = np.frombuffer(np.random.default_rng(rep * 100 + rg.count).bytes(rg.buf.size), np.uint8)
+                buf.copy_(torch.from_numpy(rg.buf))
+                out.zero_()
+            _ = torch.arange(1000, device=U.dev()).sum().item()
+        g.launch(stream)
+        torch.cuda.synchronize()
+        assert plan.status() == pmp.PMP_OK
+        for rg, flags, buf, off, out in keep:
+            got = U.as_u64(out.cpu().numpy())
+            want = oracle_of(rg, flags)
+            assert U.first_mismatch(got, want) is None, (rep, U.first_mismatch(got, want))
+    g.close()
+    plan.close()
+
+
+def test_autotune_keeps_results():
+    """The autotuner picks a compiled setting and the outputs stay exact."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    lengths = W.c4_lengths(4096, seed=931)
+    lens, wide = lengths
+    specs = [(W.from_lengths(lens[~wide], 932, False), 0), (W.from_lengths(lens[wide], 933, True), 0)]
+    k32 = U.to_dev_keys(U.keys_for(False, W.KEY_SEED32))
+    k64 = U.to_dev_keys(U.keys_for(True, W.KEY_SEED64))
+    keep, batches = _batches_for(specs, k32, k64)
+    plan = pmp.Plan(0)
+    say("case autotune")
+    best = pmp.pmp_plan_autotune(plan, batches)
+    say(f"best {best}")
+    assert best["ms"] > 0 and best["alpha"] in (32, 64, 128)
+    for rg, flags, buf, off, out in keep:
+        out.zero_()
+    pmp.pmp_hash_many(batches, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == pmp.PMP_OK
+    for rg, flags, buf, off, out in keep:
+        assert U.first_mismatch(U.as_u64(out.cpu().numpy()), oracle_of(rg, flags)) is None
+    plan.close()
