@@ -22,6 +22,8 @@ FLAGS = [
     "-fPIC",
     # packed fp32 instructions stay off (none are needed for integer work)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # private arrays stay in registers; LDS is reserved for the staging buffers
+    "-mllvm", "-disable-promote-alloca-to-lds",
     "-I" + INCLUDE,
     "-I" + CSRC,
 ]

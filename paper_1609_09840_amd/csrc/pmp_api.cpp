@@ -196,22 +196,18 @@ struct Prepared {
 
 // Check the batches, size the plan workspace, fill the descriptors and pick
 // the grid. Called with plan->mu held.
-int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, const std::vector<uint64_t>& span,
-            Prepared& P) {
+int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, Prepared& P) {
   using namespace pmp;
   const int nb = (int)list.size();
   P.nb = nb;
   std::memset(&P.a, 0, sizeof P.a);
   if (nb == 0) return PMP_OK;
-  uint64_t need = 0, work = 0;
-  for (int k = 0; k < nb; ++k) {
-    need += slots_for(list[k]->buf_bytes, (int)list[k]->wide);
-    work += list[k]->buf_bytes + (uint64_t)plan->alpha * (uint64_t)list[k]->count;
-  }
+  uint64_t need = 0;
+  for (int k = 0; k < nb; ++k) need += slots_for(list[k]->buf_bytes, (int)list[k]->wide);
   int r = plan_slots(plan, need);
   if (r) return r;
   P.bv.assign(nb, BatchArgs{});
-  uint64_t base = 0;
+  uint64_t base = 0, work = 0;
   for (int k = 0; k < nb; ++k) {
     BatchArgs& B = P.bv[k];
     std::memset(&B, 0, sizeof B);
@@ -225,7 +221,9 @@ int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, const std
     B.wide = list[k]->wide;
     B.slots = plan->slots + base;
     B.nslots = slots_for(list[k]->buf_bytes, (int)list[k]->wide);
-    B.span = span[k];
+    B.work0 = work;
+    B.work = (uint64_t)plan->alpha * (uint64_t)list[k]->count + list[k]->buf_bytes;
+    work += B.work;
     base += B.nslots;
   }
   if (nb <= 2)
@@ -243,22 +241,20 @@ int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, const std
   if (waves < 1) waves = 1;
   if (waves > max_waves) waves = max_waves;
   P.a.total_waves = (uint32_t)waves;
+  P.a.total = work;
+  P.a.share = (work + waves - 1) / waves;
   P.grid = (int)((waves + 3) / 4);
   return PMP_OK;
 }
 
 // Validate and keep the non-empty batches.
-int collect(const pmp_batch* const* in, int n_in, const uint64_t* spans, std::vector<const pmp_batch*>& list,
-            std::vector<uint64_t>& span) {
+int collect(const pmp_batch* const* in, int n_in, std::vector<const pmp_batch*>& list) {
   if (n_in < 0) return fail(PMP_E_INVALID_ARG, "negative batch count");
   list.reserve(n_in);
   for (int k = 0; k < n_in; ++k) {
     int r = check_batch(in[k]);
     if (r) return r;
-    if (in[k] && in[k]->count > 0) {
-      list.push_back(in[k]);
-      span.push_back(spans ? spans[k] : pmp::SPAN_UNKNOWN);
-    }
+    if (in[k] && in[k]->count > 0) list.push_back(in[k]);
   }
   return PMP_OK;
 }
@@ -280,18 +276,16 @@ int current_plan(pmp_plan** plan, hipStream_t stream) {
 
 namespace pmp {
 
-// Hash n batches in one launch. spans[k] (optional) is offsets[count] -
-// offsets[0] of batch k when the caller knows it.
-int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint64_t* spans, hipStream_t stream) {
+// Hash n batches in one launch.
+int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream) {
   std::vector<const pmp_batch*> list;
-  std::vector<uint64_t> span;
-  int r = collect(in, n_in, spans, list, span);
+  int r = collect(in, n_in, list);
   if (r || list.empty()) return r;
   r = current_plan(&plan, stream);
   if (r) return r;
   std::lock_guard<std::mutex> lk(plan->mu);
   Prepared P;
-  r = prepare(plan, list, span, P);
+  r = prepare(plan, list, P);
   if (r) return r;
   hipError_t e;
   if (P.nb > 2) {
@@ -325,7 +319,7 @@ namespace {
 
 int run_two(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, hipStream_t stream) {
   const pmp_batch* l[2] = {b0, b1};
-  return pmp::run_batches(plan, l, 2, nullptr, stream);
+  return pmp::run_batches(plan, l, 2, stream);
 }
 
 }  // namespace
@@ -480,7 +474,7 @@ int pmp_hash_many(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_
   if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(PMP_E_INVALID_ARG, "bad batch array");
   std::vector<const pmp_batch*> l(nbatch);
   for (int k = 0; k < nbatch; ++k) l[k] = batches + k;
-  return pmp::run_batches(plan, l.data(), nbatch, nullptr, (hipStream_t)stream);
+  return pmp::run_batches(plan, l.data(), nbatch, (hipStream_t)stream);
 }
 
 int pmp_graph_create(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_graph** out) {
@@ -489,14 +483,13 @@ int pmp_graph_create(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, p
   std::vector<const pmp_batch*> in(nbatch);
   for (int k = 0; k < nbatch; ++k) in[k] = batches + k;
   std::vector<const pmp_batch*> list;
-  std::vector<uint64_t> span;
-  int r = collect(in.data(), nbatch, nullptr, list, span);
+  int r = collect(in.data(), nbatch, list);
   if (r) return r;
   r = current_plan(&plan, nullptr);
   if (r) return r;
   std::lock_guard<std::mutex> lk(plan->mu);
   Prepared P;
-  r = prepare(plan, list, span, P);  // grows the workspace now, outside the capture
+  r = prepare(plan, list, P);  // grows the workspace now, outside the capture
   if (r) return r;
   pmp_graph* g = new pmp_graph();
   g->plan = plan;

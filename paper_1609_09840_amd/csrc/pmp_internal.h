@@ -34,11 +34,14 @@ struct BatchArgs {
   uint32_t wide;
   Slot* slots;  // ceil(buf_bytes / (128 W)) + 2 node accumulators
   uint64_t nslots;
-  uint64_t span;  // offsets[count] - offsets[0] when the host knows it, else ~0
+  uint64_t work0;  // work of the batches before this one
+  uint64_t work;   // alpha * count + buf_bytes
 };
 
-constexpr uint64_t SPAN_UNKNOWN = ~0ull;
-
+// The work of a launch is the sum over batches of alpha * count + buf_bytes:
+// string i of a batch starts at work position work0 + alpha * i + offsets[i]
+// (a byte of buffer and a string each count as work). Wave w takes
+// [w * share, (w + 1) * share) of it.
 struct KArgs {
   BatchArgs b[2];              // up to two batches travel in the arguments...
   const BatchArgs* batches;    // ...more come as a device array (else null)
@@ -46,11 +49,13 @@ struct KArgs {
   uint32_t alpha;        // per-string work in byte equivalents
   int32_t* status;       // device status word (STATUS_* bits)
   uint32_t total_waves;  // waves sharing the work
+  uint64_t total;        // work of all batches
+  uint64_t share;        // work per wave
 };
 
 // host side (pmp_api.cpp)
 int set_error(int code, const char* msg);  // sets the message pmp_last_error returns
-int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, const uint64_t* spans, hipStream_t stream);
+int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream);
 
 // kernels/launchers (pmp_kernels.hip)
 hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s);

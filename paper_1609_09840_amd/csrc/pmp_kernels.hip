@@ -1,28 +1,30 @@
 // PM+32 / PM+64 batch hashing kernels for gfx950 (wave64).
 //
-// One launch hashes a ragged batch (or two batches, one per variant). The
-// work of a batch is the sum over strings of (alpha + bytes); wave w of the
-// grid takes the w-th equal share of it, located by a 64-way search over the
-// offsets, so every wave gets the same amount of work whatever the length
-// mix, and no wave waits for another. Within its share a wave walks the
-// strings 64 at a time:
+// One launch hashes any number of ragged batches of either variant. The work
+// of a batch is alpha per string plus its buffer bytes; wave w of the grid
+// takes the w-th equal share of the launch's work and finds its first and
+// last (string, block) positions by two 64-ary searches over the offsets run
+// in lockstep, so no wave waits for another and no host pass is needed.
+// Within its share a wave walks the strings 64 at a time:
 //
-//  - strings of one 128-word block (Algorithm 1 is then one Eq. (1)
-//    evaluation) are hashed one per lane: the lane walks its string in
-//    16-byte groups, the group's keys are wave-uniform scalar loads, and the
-//    products are summed exactly with v_mad_u64_u32 plus a carry counter
-//    (deferred reduction: one fold per block, Sec. 6);
-//  - longer strings are hashed by the whole wave, G lanes per block (a lane
-//    owns 128/G consecutive words of the block and keeps their level-1 keys
-//    in registers); each block is reduced over its G lanes, folded into a
-//    field element and multiplied straight into its level-2 node's sum.
+//  - strings of at most 16 groups of 16 bytes are hashed one per lane out of
+//    the wave's LDS stage, which direct-to-LDS loads fill with their chunks
+//    (coalesced), Algorithm 1 being a single Eq. (1) evaluation for them;
+//  - strings of up to four 128-word blocks, one per group of G lanes, block
+//    by block;
+//  - longer strings by the whole wave, G lanes per block (a lane owns the
+//    16-byte pieces j, j + G, ... of its block); each block is reduced over
+//    its G lanes, folded into a field element (Sec. 6.2, Algorithm 2) and
+//    multiplied straight into its level-2 node's sum.
 //
-// Tree levels >= 2 are finished without barriers: a level-2 node whose
-// blocks all lie in one wave's share is computed by that wave; a node split
-// between waves, and every node of level >= 3, has an accumulator slot that
-// receives field elements by atomic adds with a weight counter (release /
-// acquire at agent scope); the contribution that completes the weight
-// computes the node, returns the slot to zero and climbs on.
+// Products are summed exactly (v_mad_u64_u32 with a counted carry) and
+// reduced once per block (deferred reduction). Tree levels >= 2 need no
+// barrier: a level-2 node whose blocks all lie in one wave's share is
+// computed by that wave; otherwise each contribution is added into the
+// node's accumulator slot with relaxed device atomics together with its
+// weight, and the contribution that completes the weight reads the sum back
+// (its own atomic's result carries the data dependency), computes the node,
+// returns the slot to zero and climbs on.
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
 
@@ -128,93 +130,147 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // longer strings, or strings cut by the share's ends, by the whole wave.
 constexpr uint32_t TINY_GROUPS = 16;
 constexpr int64_t MEDIUM_BLOCKS = 4;
-constexpr int SHORT_BATCH = 8;  // 16-byte groups per batch of loads in the one-per-lane path
 
 // ---------------------------------------------------------------------------
-// Strings of one block, one per lane. `act` marks lanes with such a string.
-// Each lane walks its string in batches of K 16-byte groups whose loads are
-// all in flight together; the group's keys are wave-uniform scalar loads.
+// Strings of at most TINY_GROUPS groups, one per lane, read from LDS.
+//
+// Per-lane loads of 64 unrelated strings are slow (64 cache lines per load
+// instruction, and few in flight per lane), so the wave first copies the
+// 16-byte chunks that hold its tiny strings into its LDS stage with
+// direct-to-LDS loads. Each lane reserves slots c0 .. c0 + ns - 1 of the
+// stage in lane order (its chunks plus room for the pad word) and writes the
+// numbers of its chunks, relative to the first string's chunk, into a slot
+// table; load instruction k then fills slots 64k .. 64k + 63, and since
+// consecutive slots mostly belong to one string the loads are coalesced.
+// Lanes that do not fit go in a further pass. Each lane then writes the pad
+// (Sec. 4: a byte 0x01, zeros to the end of its slots) into its own copy, so
+// that the words of its padded string read straight out of the stage; words
+// past the padded end are dropped by one compare each. The group's keys are
+// wave-uniform LDS reads (broadcast) and the products are summed exactly with
+// v_mad_u64_u32 plus a carry counter (one fold per string).
+constexpr uint32_t STAGE_CHUNKS = 768;             // 12 KiB of string bytes per wave
+constexpr uint32_t STAGE_BYTES = 16 * STAGE_CHUNKS;
+constexpr uint32_t STAGE_SLACK = 512;              // reads past a lane's slots stay in the wave's region
+constexpr uint32_t NO_CHUNK = ~0u;
+
+__device__ __forceinline__ void wait_vm0() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+__device__ __forceinline__ void wait_lgkm0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 template <bool WIDE>
-__device__ void short_strings(const BatchArgs& B, int64_t i, bool act, int64_t o0, int64_t len) {
+__device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table, int64_t i,
+                              bool act, int64_t o0, int64_t len) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
-  constexpr int WPG = 16 / W;  // words per 16-byte group
-  constexpr int K = SHORT_BATCH;  // groups per batch of loads
-  const uint8_t* lo = B.buf;
-  const uint8_t* hi = B.buf + B.buf_bytes;
-  const uint8_t* safe = (const uint8_t*)B.keys;
+  uint64_t todo = __ballot(act);
+  if (!todo) return;
+  const int lane = lane_id();
   const uint8_t* s = B.buf + (act ? o0 : 0);
-  const uint32_t sh = (uint32_t)((uintptr_t)s & 3u);
-  const uint8_t* a4 = s - sh;
-  const int64_t nw = act ? len / W + 1 : 0;
-  const int64_t rlen = act ? len : -1;  // inactive lanes mask every word away
-  const uint32_t ng = (uint32_t)((nw + WPG - 1) / WPG);
-  const uint32_t maxg = wave_max(ng);
-  if (maxg == 0) return;
+  const uint32_t lead = (uint32_t)((uintptr_t)s & 15u);
+  const uint64_t a16 = (uint64_t)(uintptr_t)(s - lead);
+  const uint32_t sh = lead & 3u;
+  const uint32_t ulen = act ? (uint32_t)len : 0u;  // < 256 here
+  const uint32_t pbytes = act ? (ulen / W + 1) * W : 0u;  // padded length
+  // chunks [a16, a16 + 16 nl) hold the string (none for an empty one: its
+  // buffer may be empty); ns slots leave room for the pad word
+  const uint32_t nl = act && ulen > 0 ? (lead + ulen + 15) / 16 : 0u;
+  const uint32_t ns = act ? (lead + ulen + W + 15) / 16 : 0u;
+  uint64_t total = 0;
+  const uint32_t c0 = (uint32_t)wave_excl_scan(ns, &total);
   const typename T::key_t* __restrict__ keys = (const typename T::key_t*)B.keys;
-
-  typename T::Sum acc;
-  zero(acc);
-  P64 p;
-  zero(p);
-  for (uint32_t g0 = 0; g0 < maxg; g0 += K) {
-    uint32_t d[4 * K + 1];
-    uint32_t part = 0;  // groups that straddle the buffer edges
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint32_t g = g0 + k;
-      const uint8_t* pa = a4 + 16 * (int64_t)g;
-      // the group after the last one supplies the last group's realignment
-      const bool need = g < ng + (sh ? 1u : 0u);
-      const bool full = need && inside(pa, 16, lo, hi);
-      Q q = load16(full ? pa : safe);
-      if (need && !full) part |= 1u << k;
-      d[4 * k] = full ? q.d[0] : 0u;
-      d[4 * k + 1] = full ? q.d[1] : 0u;
-      d[4 * k + 2] = full ? q.d[2] : 0u;
-      d[4 * k + 3] = full ? q.d[3] : 0u;
+  const auto* lds1 = (__attribute__((address_space(3))) uint8_t*)stage;
+  uint32_t base = 0;  // first slot number of this pass
+  while (todo) {
+    const bool mine = (todo >> lane) & 1ull;
+    // chunk numbers are kept relative to the pass's first string, in 32 bits
+    const int first = __ffsll((unsigned long long)todo) - 1;
+    const uint64_t tb = uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a16, first)) |
+                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a16 >> 32), first) << 32));
+    const uint64_t rel = (a16 - tb) >> 4;
+    const bool in = mine && c0 + ns - base <= STAGE_CHUNKS && rel + nl < (1ull << 32);
+    const uint64_t pm = __ballot(in);
+    const uint32_t tp = wave_max(in ? c0 + ns - base : 0u);  // slots used by this pass
+    wait_lgkm0();  // the previous pass is done reading the stage
+    // (also written with inline asm, so that the compiler does not wait for
+    // the previous tile's output stores before each entry)
+    if (in) {
+      const uint32_t ta = lds_addr(table) + 4 * (c0 - base);
+      for (uint32_t t = 0; t < ns; ++t) {
+        const uint32_t v = t < nl ? (uint32_t)rel + t : NO_CHUNK;
+        asm volatile("ds_write_b32 %0, %1" ::"v"(ta + 4 * t), "v"(v) : "memory");
+      }
     }
-    {  // first dword after the batch (realignment of the last group)
-      const uint8_t* pa = a4 + 16 * (int64_t)(g0 + K);
-      const bool need = sh && g0 + K - 1 < ng;
-      const bool full = need && inside(pa, 4, lo, hi);
-      const uint32_t e = *(const uint32_t*)__builtin_assume_aligned(full ? pa : safe, 4);
-      d[4 * K] = full ? e : (need ? load4_guarded(pa, lo, hi) : 0u);
-    }
-    if (part) {
+    // Four table entries per read: the table is read with inline asm (its
+    // wait included) because the compiler would otherwise wait for every
+    // outstanding direct-to-LDS load before each LDS read.
+    for (uint32_t k0 = 0; k0 * 64 < tp; k0 += 4) {
+      const uint32_t ta = lds_addr(table) + 4 * (k0 * 64 + (uint32_t)lane);
+      uint32_t e[4];
+      asm volatile(
+          "ds_read_b32 %0, %4\n\tds_read_b32 %1, %4 offset:256\n\tds_read_b32 %2, %4 offset:512\n\t"
+          "ds_read_b32 %3, %4 offset:768\n\ts_waitcnt lgkmcnt(0)"
+          : "=&v"(e[0]), "=&v"(e[1]), "=&v"(e[2]), "=&v"(e[3])
+          : "v"(ta)
+          : "memory");
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (part & (1u << k)) {
-          Q q = load16_slow(a4 + 16 * (int64_t)(g0 + k), lo, hi);
-          d[4 * k] = q.d[0];
-          d[4 * k + 1] = q.d[1];
-          d[4 * k + 2] = q.d[2];
-          d[4 * k + 3] = q.d[3];
-        }
+      for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t k = k0 + u;
+        if (k * 64 >= tp) break;  // uniform
+        const uint32_t j = k * 64 + (uint32_t)lane;
+        if (j < tp && e[u] != NO_CHUNK)
+          __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)(tb + 16ull * e[u]),
+                                           (__attribute__((address_space(3))) void*)(lds1 + 1024 * k), 16, 0, 0);
+      }
     }
+    wait_vm0();
+    // the pad in this lane's own slots: 0x01 after the string, zeros to the end
+    const uint32_t r0 = 16 * (c0 - base);  // this lane's first slot, in bytes
+    if (in) {
+      const uint32_t z0 = r0 + lead + ulen, zw = z0 & ~3u, zb = 8 * (z0 & 3u);
+      uint32_t* dw = (uint32_t*)(stage + zw);
+      const uint32_t keep = zb ? (dw[0] & ((1u << zb) - 1u)) : 0u;
+      dw[0] = keep | (1u << zb);
+      for (uint32_t q = zw + 4; q < r0 + 16 * ns; q += 4) *(uint32_t*)(stage + q) = 0u;
+    }
+    const uint32_t maxg = wave_max(in ? (pbytes + 15) / 16 : 0u);
+    const uint32_t p0 = in ? r0 + (lead & ~3u) : 0u;
+    const uint32_t pe = in ? pbytes : 0u;  // words at or past pe are not part of the padded string
+    typename T::Sum acc;
+    zero(acc);
+    P64 p;
+    zero(p);
+    for (uint32_t g = 0; g < maxg; ++g) {
+      const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
+      uint32_t d[5];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint32_t g = g0 + k;
-      if (g >= maxg) break;  // uniform
+      for (int u = 0; u < 5; ++u) d[u] = q[u];
       uint32_t x[4];
-      group_words<WIDE>(d + 4 * k, sh, rlen - 16 * (int64_t)g, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t v = align_bytes(d[u + 1], d[u], sh);
+        x[u] = 16 * g + 4 * u < pe ? v : 0u;
+      }
       if constexpr (WIDE) {
-        const uint64_t* kk = keys + 2 * g;
+        const uint64_t* kk = lk + 2 * g;  // level-1 keys, staged in LDS
         mac64_sv(p, kk[0], x[0], x[1]);
         mac64_sv(p, kk[1], x[2], x[3]);
       } else {
-        const uint32_t* kk = keys + 4 * g;
+        const uint64_t* kk = lk + 4 * g;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) mac_sv(acc.lo, acc.hi, kk[u], x[u]);
+        for (int u = 0; u < 4; ++u) mac_sv(acc.lo, acc.hi, (uint32_t)kk[u], x[u]);
       }
     }
-  }
-  if (act) {
-    typename T::Sum tot;
-    if constexpr (WIDE) tot = collapse(p);
-    else tot = acc;
-    add_word(tot, (uint64_t)keys[8 * BLOCK]);  // b_1
-    store_out<WIDE>(B, i, reduce(tot));
+    if (in) {
+      typename T::Sum tot;
+      if constexpr (WIDE) tot = collapse(p);
+      else tot = acc;
+      add_word(tot, (uint64_t)keys[8 * BLOCK]);  // b_1
+      store_out<WIDE>(B, i, reduce(tot));
+    }
+    todo &= ~pm;
+    base += tp;
   }
 }
 
@@ -509,47 +565,73 @@ __device__ void long_string(const KArgs& A, const BatchArgs& B, const uint64_t* 
 struct Pos {
   int64_t i, c;
 };
-__device__ __forceinline__ uint64_t fpos(const int64_t* off, int64_t base, uint32_t alpha, int64_t i) {
-  return (uint64_t)alpha * (uint64_t)i + (uint64_t)(off[i] - base);
+// Work position of the start of string i: alpha per string before it plus
+// its byte offset.
+__device__ __forceinline__ uint64_t fpos(const int64_t* off, uint32_t alpha, int64_t i) {
+  return (uint64_t)alpha * (uint64_t)i + (uint64_t)off[i];
 }
+// The (string, block) positions of work offsets x0 <= x1 within a batch:
+// the first block starting at or after each. Block 0 of string i starts at
+// fpos(i); block c >= 1 at fpos(i) + alpha + (c - 1) * 128 W. Both 64-ary
+// searches run in lockstep so that their loads share the round trips.
 template <int W>
-__device__ Pos locate(const BatchArgs& B, uint32_t alpha, uint64_t x) {
+__device__ void locate2(const BatchArgs& B, uint32_t alpha, uint64_t x0, uint64_t x1, Pos& p0, Pos& p1) {
   const int64_t* off = B.offsets;
   const int64_t n = B.count;
-  const int64_t base = off[0];
   const int lane = lane_id();
-  if (x == 0) return Pos{0, 0};
-  if (x >= fpos(off, base, alpha, n)) return Pos{n, 0};
-  int64_t lo = 0, hi = n;  // invariant: f(lo) <= x
-  while (hi - lo >= 64) {
-    const int64_t step = (hi - lo + 63) / 64;
-    const int64_t p = lo + (int64_t)lane * step;
-    const bool ok = p <= hi && fpos(off, base, alpha, p) <= x;
-    const uint64_t m = __ballot(ok) | 1ull;
-    const int l = 63 - __clzll((long long)m);
-    const int64_t nlo = lo + (int64_t)l * step;
-    const int64_t nhi = nlo + step - 1;
-    lo = nlo;
-    hi = nhi < hi ? nhi : hi;
+  const uint64_t fn = fpos(off, alpha, n);
+  // invariant: fpos(lo) <= x (or lo = 0)
+  int64_t lo0 = 0, hi0 = n, lo1 = 0, hi1 = n;
+  while (hi0 - lo0 >= 64 || hi1 - lo1 >= 64) {
+    const int64_t st0 = (hi0 - lo0 + 63) / 64, st1 = (hi1 - lo1 + 63) / 64;
+    const int64_t q0 = lo0 + (int64_t)lane * st0, q1 = lo1 + (int64_t)lane * st1;
+    const bool a0 = hi0 - lo0 >= 64 && q0 <= hi0, a1 = hi1 - lo1 >= 64 && q1 <= hi1;
+    const uint64_t f0 = a0 ? fpos(off, alpha, q0) : 0, f1 = a1 ? fpos(off, alpha, q1) : 0;
+    if (hi0 - lo0 >= 64) {
+      const uint64_t m = __ballot(a0 && f0 <= x0) | 1ull;
+      const int64_t nlo = lo0 + (int64_t)(63 - __clzll((long long)m)) * st0, nhi = nlo + st0 - 1;
+      lo0 = nlo;
+      hi0 = nhi < hi0 ? nhi : hi0;
+    }
+    if (hi1 - lo1 >= 64) {
+      const uint64_t m = __ballot(a1 && f1 <= x1) | 1ull;
+      const int64_t nlo = lo1 + (int64_t)(63 - __clzll((long long)m)) * st1, nhi = nlo + st1 - 1;
+      lo1 = nlo;
+      hi1 = nhi < hi1 ? nhi : hi1;
+    }
   }
   {
-    const int64_t p = lo + lane;
-    const bool ok = p <= hi && fpos(off, base, alpha, p) <= x;
-    const uint64_t m = __ballot(ok) | 1ull;
-    lo += 63 - __clzll((long long)m);
+    const int64_t q0 = lo0 + lane, q1 = lo1 + lane;
+    const bool a0 = q0 <= hi0, a1 = q1 <= hi1;
+    const uint64_t f0 = a0 ? fpos(off, alpha, q0) : 0, f1 = a1 ? fpos(off, alpha, q1) : 0;
+    lo0 += 63 - __clzll((long long)(__ballot(a0 && f0 <= x0) | 1ull));
+    lo1 += 63 - __clzll((long long)(__ballot(a1 && f1 <= x1) | 1ull));
   }
-  const int64_t i = uni64s(lo);
-  if (i >= n) return Pos{n, 0};
-  const uint64_t fi = fpos(off, base, alpha, i);
-  if (x <= fi) return Pos{i, 0};
-  const uint64_t y = x - fi;
-  const int64_t len = off[i + 1] - off[i];
-  const int64_t C1 = ((len / W + 1) + BLOCK - 1) / BLOCK;
-  int64_t c = 1;
-  if (y > alpha) c = (int64_t)((y - alpha + BLOCK * W - 1) / (BLOCK * W));
-  if (c < 1) c = 1;
-  if (c >= C1) return Pos{i + 1, 0};
-  return Pos{i, c};
+  const int64_t i0 = uni64s(lo0), i1 = uni64s(lo1);
+  // string i0 / i1 and the next offsets, loaded together
+  const int64_t j = lane == 0 ? i0 : i1;
+  const bool ld = lane < 2 && j < n;
+  const int64_t oa = ld ? off[j] : 0, ob = ld ? off[j + 1] : 0;
+  auto finish = [&](uint64_t x, int64_t i, int l) -> Pos {
+    if (x == 0) return Pos{0, 0};
+    if (x >= fn || i >= n) return Pos{n, 0};
+    const int64_t o0 = uni64s((int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)oa, l)) |
+                                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)oa >> 32), l) << 32)));
+    const int64_t o1 = uni64s((int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ob, l)) |
+                                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)ob >> 32), l) << 32)));
+    const uint64_t fi = (uint64_t)alpha * (uint64_t)i + (uint64_t)o0;
+    if (x <= fi) return Pos{i, 0};
+    const uint64_t y = x - fi;
+    const int64_t len = o1 - o0;
+    const int64_t C1 = ((len / W + 1) + BLOCK - 1) / BLOCK;
+    int64_t c = 1;
+    if (y > alpha) c = (int64_t)((y - alpha + BLOCK * W - 1) / (BLOCK * W));
+    if (c < 1) c = 1;
+    if (c >= C1) return Pos{i + 1, 0};
+    return Pos{i, c};
+  };
+  p0 = finish(x0, i0, 0);
+  p1 = finish(x1, i1, 1);
 }
 
 // All blocks in [ps, pe) of one batch, 64 strings at a time.
@@ -627,7 +709,8 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, bool med,
 
 // All blocks in [ps, pe) of one batch, 64 strings at a time.
 template <bool WIDE, int G>
-__device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk, Pos ps, Pos pe) {
+__device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table,
+                          Pos ps, Pos pe) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
   constexpr int WPG = 16 / W;
@@ -659,7 +742,7 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
     const bool med = whole && !tiny && C1 <= MEDIUM_BLOCKS;
     const bool lng = ok && !tiny && !med && lo_c < hi_c;
 
-    short_strings<WIDE>(B, i, tiny, o0, len);
+    short_strings<WIDE>(B, lk, stage, table, i, tiny, o0, len);
     medium_strings<WIDE, G>(B, lk, med, i, o0, len, C1);
 
     // the long strings, one at a time by the whole wave
@@ -680,29 +763,27 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
   }
 }
 
-// Work of a batch: alpha per string plus its bytes.
-__device__ __forceinline__ uint64_t batch_work(int64_t count, uint64_t span, const int64_t* offsets,
-                                               uint32_t alpha) {
-  if (count <= 0) return 0;
-  if (span == SPAN_UNKNOWN) {
-    const int64_t d = offsets[count] - offsets[0];
-    span = d > 0 ? (uint64_t)d : 0;
-  }
-  return (uint64_t)alpha * (uint64_t)count + span;
-}
-
-// Work of batch b (lane-varying b). The argument copies of the first two
+// Batch b of the launch (b uniform). The argument copies of the first two
 // batches are read by selection, never by a dynamic index, which would move
 // the whole argument block to scratch.
-__device__ __forceinline__ uint64_t batch_work_at(const KArgs& A, uint32_t b) {
-  if (b >= A.nbatch) return 0;
-  if (A.batches) {
-    const BatchArgs* B = A.batches + b;
-    return batch_work(B->count, B->span, B->offsets, A.alpha);
-  }
-  const bool one = b != 0;
-  return batch_work(one ? A.b[1].count : A.b[0].count, one ? A.b[1].span : A.b[0].span,
-                    one ? A.b[1].offsets : A.b[0].offsets, A.alpha);
+__device__ __forceinline__ BatchArgs batch_at(const KArgs& A, uint32_t b) {
+  BatchArgs B = A.batches ? A.batches[b] : (b ? A.b[1] : A.b[0]);
+  // a descriptor read from global memory is wave-uniform, but the compiler
+  // cannot tell: keep its fields in scalar registers so that addresses built
+  // from them (key tables above all) use scalar loads
+  B.buf = (const uint8_t*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.buf);
+  B.buf_bytes = uni64(B.buf_bytes);
+  B.offsets = (const int64_t*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.offsets);
+  B.count = uni64s(B.count);
+  B.keys = (const void*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.keys);
+  B.out = (void*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.out);
+  B.flags = uni(B.flags);
+  B.wide = uni(B.wide);
+  B.slots = (Slot*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.slots);
+  B.nslots = uni64(B.nslots);
+  B.work0 = uni64(B.work0);
+  B.work = uni64(B.work);
+  return B;
 }
 
 template <int G32, int G64>
@@ -710,38 +791,41 @@ __global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
   // each wave keeps the level-1 and level-2 keys of the batch it works on in
   // its own LDS region, as 64-bit words
   __shared__ uint64_t lkeys[4][2 * BLOCK];
+  // the direct-to-LDS loads write only `stages`: the compiler then waits for
+  // them before reads of `stages` alone, not before those of the tables
+  __shared__ __attribute__((aligned(16))) uint8_t stages[4][STAGE_BYTES + STAGE_SLACK];
+  __shared__ uint32_t tables[4][STAGE_CHUNKS];
   const int lane = lane_id();
   uint64_t* lk = lkeys[threadIdx.x / 64];
+  uint8_t* stage = stages[threadIdx.x / 64];
+  uint32_t* table = tables[threadIdx.x / 64];
   const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (w >= A.total_waves) return;
+  const uint64_t x0 = w * A.share < A.total ? w * A.share : A.total;
+  const uint64_t x1 = x0 + A.share < A.total ? x0 + A.share : A.total;
+  if (x0 >= x1) return;
   const uint32_t nb = A.nbatch;
-  // total work, 64 batches at a time
-  uint64_t total = 0;
+  // the batches that overlap [x0, x1), in order, 64 descriptors at a time
   for (uint32_t base = 0; base < nb; base += 64) {
-    uint64_t t = 0;
-    (void)wave_excl_scan(batch_work_at(A, base + (uint32_t)lane), &t);
-    total += t;
-  }
-  const uint64_t x0 = (uint64_t)(((u128)total * w) / A.total_waves);
-  const uint64_t x1 = (uint64_t)(((u128)total * (w + 1)) / A.total_waves);
-  // the batches that overlap [x0, x1), in order
-  uint64_t start = 0;
-  for (uint32_t base = 0; base < nb && start < x1; base += 64) {
-    const uint64_t wk = batch_work_at(A, base + (uint32_t)lane);
-    uint64_t ct = 0;
-    const uint64_t p = start + wave_excl_scan(wk, &ct);
-    uint64_t m = __ballot(wk > 0 && p < x1 && p + wk > x0);
+    const uint32_t b = base + (uint32_t)lane;
+    uint64_t s0 = 0, sw = 0;
+    if (b < nb) {
+      if (A.batches) {
+        s0 = A.batches[b].work0;
+        sw = A.batches[b].work;
+      } else {
+        s0 = b ? A.b[1].work0 : A.b[0].work0;
+        sw = b ? A.b[1].work : A.b[0].work;
+      }
+    }
+    uint64_t m = __ballot(b < nb && sw > 0 && s0 < x1 && s0 + sw > x0);
+    const bool past = __ballot(b < nb && s0 >= x1) != 0;  // later chunks start past x1 too
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const uint32_t bi = base + (uint32_t)l;
-      const uint64_t bstart = uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)p, l)) |
-                                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(p >> 32), l) << 32));
-      const uint64_t bw = uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wk, l)) |
-                                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(wk >> 32), l) << 32));
-      const BatchArgs B = A.batches ? A.batches[bi] : (bi ? A.b[1] : A.b[0]);
-      const uint64_t lo = x0 > bstart ? x0 - bstart : 0;
-      const uint64_t hi = x1 < bstart + bw ? x1 - bstart : bw;
+      const BatchArgs B = batch_at(A, base + (uint32_t)l);
+      const uint64_t lo = x0 > B.work0 ? x0 - B.work0 : 0;
+      const uint64_t hi = x1 < B.work0 + B.work ? x1 - B.work0 : B.work;
       // this batch's keys into the wave's LDS region
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -751,16 +835,17 @@ __global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      Pos ps, pe;
       if (B.wide) {
-        const Pos ps = locate<8>(B, A.alpha, lo), pe = locate<8>(B, A.alpha, hi);
-        run_range<true, G64>(A, B, lk, ps, pe);
+        locate2<8>(B, A.alpha, lo, hi, ps, pe);
+        run_range<true, G64>(A, B, lk, stage, table, ps, pe);
       } else {
-        const Pos ps = locate<4>(B, A.alpha, lo), pe = locate<4>(B, A.alpha, hi);
-        run_range<false, G32>(A, B, lk, ps, pe);
+        locate2<4>(B, A.alpha, lo, hi, ps, pe);
+        run_range<false, G32>(A, B, lk, stage, table, ps, pe);
       }
       __builtin_amdgcn_wave_barrier();  // all lanes done with the keys before the next batch's
     }
-    start += ct;
+    if (past) break;
   }
 }
 

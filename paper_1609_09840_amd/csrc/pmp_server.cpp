@@ -38,7 +38,7 @@ double now_us() {
 struct Req {
   uint64_t ticket = 0;
   pmp_request r{};
-  uint64_t span = pmp::SPAN_UNKNOWN;
+  uint64_t span = 0;  // payload bytes of the request (host requests), for the statistics
   uint64_t stage_bytes = 0;  // arena bytes for payload + offsets (host requests)
   uint64_t out_bytes = 0;
   double t_submit = 0, t_done = 0;
@@ -86,7 +86,6 @@ namespace {
 int launch_lane(pmp_server* S, Lane& L) {
   std::vector<pmp_batch> b(L.reqs.size());
   std::vector<const pmp_batch*> bp(L.reqs.size());
-  std::vector<uint64_t> spans(L.reqs.size());
   uint64_t front = 0, out_lo = L.arena, out_hi = L.arena;
   bool host_any = false;
   L.out_at.assign(L.reqs.size(), 0);
@@ -115,13 +114,12 @@ int launch_lane(pmp_server* S, Lane& L) {
       L.out_at[k] = out_lo;
       x.out = L.d_arena + out_lo;
     }
-    spans[k] = L.reqs[k]->span;
     bp[k] = &x;
   }
   hipError_t e = hipSuccess;
   if (host_any && front) e = hipMemcpyAsync(L.d_arena, L.h_stage, front, hipMemcpyHostToDevice, L.stream);
   if (e != hipSuccess) return PMP_E_HIP;
-  int rc = pmp::run_batches(L.plan, bp.data(), (int)bp.size(), spans.data(), L.stream);
+  int rc = pmp::run_batches(L.plan, bp.data(), (int)bp.size(), L.stream);
   if (rc) return rc;
   if (host_any && out_hi > out_lo)
     e = hipMemcpyAsync(L.h_stage + out_lo, L.d_arena + out_lo, out_hi - out_lo, hipMemcpyDeviceToHost, L.stream);
@@ -141,7 +139,7 @@ void finish_lane(pmp_server* S, Lane& L, int rc) {
     if (rc == PMP_OK) {
       S->lat_us.push_back(t - q->t_submit);
       S->done_n++;
-      S->bytes += q->span == pmp::SPAN_UNKNOWN ? q->r.buf_bytes : q->span;
+      S->bytes += q->r.device_resident ? q->r.buf_bytes : q->span;
       S->last_done = t;
     }
   }
