@@ -153,11 +153,14 @@ constexpr uint32_t STAGE_BYTES = 16 * STAGE_CHUNKS;
 constexpr uint32_t STAGE_SLACK = 512;              // reads past a lane's slots stay in the wave's region
 constexpr uint32_t NO_CHUNK = ~0u;
 
-__device__ __forceinline__ void wait_vm0() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// s_waitcnt through the builtin, so that the compiler's own wait insertion
+// knows that every outstanding load (direct-to-LDS ones included) is done.
+// gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+__device__ __forceinline__ void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
-__device__ __forceinline__ void wait_lgkm0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 template <bool WIDE>
 __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table, int64_t i,
@@ -378,30 +381,42 @@ __device__ void climb(const KArgs& A, const BatchArgs& B, int64_t i, uint64_t sb
 // pieces j, j + G, j + 2G, ... of its block, so for each load the G lanes of
 // a group read 16 G contiguous bytes. blk is the block start moved back by sh
 // (4-aligned); piece P is bytes [16 P, 16 P + 16) of the block, read as
-// dwords D0..D4 at blk + 16 P and realigned by sh bytes. lk holds the
-// level-1 keys in LDS (as 64-bit words). All loads are issued before the
-// first product so that they are in flight together. TAIL: the block may be
-// inactive (act) or run past the string end (rem = string bytes from the
-// block start); its words are masked to the padded string of Sec. 4. The
-// caller guarantees that every byte read lies inside the buffer.
+// dwords D0..D4 at blk + 16 P and realigned by sh bytes. block_loads issues
+// all of a lane's loads at once (the caller guarantees that every byte read
+// lies inside readable memory); block_sum turns them into the exact sum of
+// key times word. lk holds the level-1 keys in LDS (as 64-bit words). TAIL:
+// the block may be inactive (act) or run past the string end (rem = string
+// bytes from the block start); its words are masked to the padded string of
+// Sec. 4.
+template <bool WIDE, int G>
+struct Pieces {
+  static constexpr int NL = BLOCK * Tr<WIDE>::W / 16 / G;  // pieces per lane
+  uint32_t d[NL][5];
+};
+
+template <bool WIDE, int G>
+__device__ __forceinline__ void block_loads(Pieces<WIDE, G>& P, const uint8_t* blk, int j, uint32_t sh) {
+#pragma unroll
+  for (int t = 0; t < Pieces<WIDE, G>::NL; ++t) {
+    const uint8_t* pa = blk + 16 * (t * G + j);
+    Q q = load16(pa);
+    P.d[t][0] = q.d[0];
+    P.d[t][1] = q.d[1];
+    P.d[t][2] = q.d[2];
+    P.d[t][3] = q.d[3];
+    // (loaded even when sh = 0, when it is not needed: a load under a
+    // condition would make the compiler drain every load before its use)
+    P.d[t][4] = *(const uint32_t*)__builtin_assume_aligned(pa + 16, 4);
+  }
+}
+
 template <bool WIDE, int G, bool TAIL>
-__device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const uint8_t* blk, int j, uint32_t sh,
+__device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G>& P, int j, uint32_t sh,
                                                             const uint64_t* lk, bool act, int64_t rem) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
-  constexpr int WPP = 16 / W;             // words per piece
-  constexpr int NL = BLOCK * W / 16 / G;  // pieces per lane
-  uint32_t d[NL][5];
-#pragma unroll
-  for (int t = 0; t < NL; ++t) {
-    const uint8_t* pa = blk + 16 * (t * G + j);
-    Q q = load16(pa);
-    d[t][0] = q.d[0];
-    d[t][1] = q.d[1];
-    d[t][2] = q.d[2];
-    d[t][3] = q.d[3];
-    d[t][4] = sh ? *(const uint32_t*)__builtin_assume_aligned(pa + 16, 4) : 0u;
-  }
+  constexpr int WPP = 16 / W;  // words per piece
+  constexpr int NL = Pieces<WIDE, G>::NL;
   const int64_t r = act ? rem : -(int64_t)(BLOCK * W) - 64;  // inactive: everything masked
   typename T::Sum acc;
   P64 p;
@@ -411,10 +426,10 @@ __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const uint8_t* blk, 
   for (int t = 0; t < NL; ++t) {
     uint32_t x[4];
     if constexpr (TAIL) {
-      group_words<WIDE>(d[t], sh, r - 16 * (int64_t)(t * G + j), x);
+      group_words<WIDE>(P.d[t], sh, r - 16 * (int64_t)(t * G + j), x);
     } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[t][u + 1], d[t][u], sh);
+      for (int u = 0; u < 4; ++u) x[u] = align_bytes(P.d[t][u + 1], P.d[t][u], sh);
     }
     const uint64_t* kp = lk + WPP * (t * G + j);
     if constexpr (WIDE) {
@@ -468,42 +483,55 @@ __device__ typename Tr<WIDE>::Sum block_guarded(const uint8_t* blk, int j, uint3
 
 // Exact sum over blocks c in [bl, bh) of level-2 node `node` of
 // a_{2, c - 128 node} * f_1(block c), for a string of len bytes at s, G lanes
-// per block. Every lane returns the whole wave's sum.
+// per block, 64 / G blocks per step. The loads of step n + 1 are issued
+// before step n is summed (software pipelining: one step in flight while the
+// other is computed); a step that touches the buffer's edges is read piece
+// by piece instead. Every lane returns the whole wave's sum.
 template <bool WIDE, int G>
 __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint64_t* lk, const uint8_t* s, int64_t len,
                                               int64_t node, int64_t bl, int64_t bh) {
   using T = Tr<WIDE>;
   using Sum = typename T::Sum;
   constexpr int W = T::W;
-  constexpr int NL = BLOCK * W / 16 / G;
   constexpr int CPS = 64 / G;  // blocks per wave step
-  static_assert(NL >= 1, "tile too wide");
+  static_assert(Pieces<WIDE, G>::NL >= 1, "tile too wide");
   const int lane = lane_id();
   const int g = lane / G, j = lane % G;
   const uint8_t* lo = B.buf;
   const uint8_t* hi = B.buf + B.buf_bytes;
+  const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
   const uint32_t sh = uni((uint32_t)((uintptr_t)s & 3u));
   const uint8_t* a4 = s - sh;
   const int64_t nb = node * BLOCK;
   const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
+  // a step is read with plain loads when all of its bytes lie in the buffer
+  auto plain = [&](int64_t c0) {
+    const uint8_t* step_lo = a4 + c0 * (int64_t)(BLOCK * W);
+    const uint8_t* step_hi = a4 + (c0 + CPS) * (int64_t)(BLOCK * W) + 4;
+    return c0 < bh && step_lo >= lo && step_hi <= hi;  // uniform
+  };
 
   Sum acc2;
   zero(acc2);
+  Pieces<WIDE, G> nxt;
+  bool have = plain(bl);
+  block_loads<WIDE, G>(nxt, have ? a4 + (bl + g) * (int64_t)(BLOCK * W) : safe, j, sh);
   for (int64_t c0 = bl; c0 < bh; c0 += CPS) {
     // keys stay in LDS: reading them again each step keeps registers free
     asm volatile("" ::: "memory");
+    const Pieces<WIDE, G> cur = nxt;
+    const bool cur_loaded = have;
+    have = plain(c0 + CPS);
+    block_loads<WIDE, G>(nxt, have ? a4 + (c0 + CPS + g) * (int64_t)(BLOCK * W) : safe, j, sh);
     const int64_t c = c0 + g;
     const bool act = c < bh;
     const uint8_t* blk = a4 + c * (int64_t)(BLOCK * W);
-    const uint8_t* step_lo = a4 + c0 * (int64_t)(BLOCK * W);
-    const uint8_t* step_hi = a4 + (c0 + CPS) * (int64_t)(BLOCK * W) + 4;
-    const bool tail = c0 + CPS >= bh;                // uniform
-    const bool out = step_lo < lo || step_hi > hi;   // uniform, only at the buffer edges
+    const bool tail = c0 + CPS >= bh;  // uniform
     const int64_t rem = len - c * (int64_t)(BLOCK * W);
     Sum blk_sum;
-    if (out) blk_sum = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
-    else if (tail) blk_sum = block_sum<WIDE, G, true>(blk, j, sh, lk, act, rem);
-    else blk_sum = block_sum<WIDE, G, false>(blk, j, sh, lk, true, 0);
+    if (!cur_loaded) blk_sum = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
+    else if (tail) blk_sum = block_sum<WIDE, G, true>(cur, j, sh, lk, act, rem);
+    else blk_sum = block_sum<WIDE, G, false>(cur, j, sh, lk, true, 0);
     group_sum<G>(blk_sum);
     add_word(blk_sum, b1);
     const Fe z = reduce(blk_sum);
@@ -652,7 +680,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, bool med,
   const int g = lane / G, j = lane % G;
   const uint8_t* lo = B.buf;
   const uint8_t* hi = B.buf + B.buf_bytes;
-  const uint8_t* safe = (const uint8_t*)B.keys;  // 128 W + 4 readable bytes
+  const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
   const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
   const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
   uint64_t m = __ballot(med);
@@ -682,15 +710,26 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, bool med,
     Sum acc2;
     zero(acc2);
     Fe res = {0, 0};
+    // block c of the group's string is read with plain loads when it lies in
+    // the buffer; block c + 1 is loaded while block c is summed
+    auto plain = [&](uint32_t c) {
+      return (int64_t)c < sc && inside(a4 + (int64_t)c * (BLOCK * W), BLOCK * W + 4, lo, hi);
+    };
+    Pieces<WIDE, G> nxt;
+    bool have = plain(0);
+    block_loads<WIDE, G>(nxt, have ? a4 : safe, j, sh);
     for (uint32_t c = 0; c < nsteps; ++c) {
       asm volatile("" ::: "memory");  // keys stay in LDS
+      const Pieces<WIDE, G> cur = nxt;
+      const bool cur_loaded = have;
+      have = plain(c + 1);
+      block_loads<WIDE, G>(nxt, have ? a4 + (int64_t)(c + 1) * (BLOCK * W) : safe, j, sh);
       const bool act = (int64_t)c < sc;
       const uint8_t* blk = act ? a4 + (int64_t)c * (BLOCK * W) : safe;
       const int64_t rem = sl - (int64_t)c * (BLOCK * W);
-      const bool inb = !act || inside(blk, BLOCK * W + 4, lo, hi);
       Sum bs;
-      if (__ballot(!inb)) bs = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
-      else bs = block_sum<WIDE, G, true>(blk, j, sh, lk, act, rem);
+      if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
+      else bs = block_sum<WIDE, G, true>(cur, j, sh, lk, act, rem);
       group_sum<G>(bs);
       add_word(bs, b1);
       const Fe z = reduce(bs);
@@ -763,6 +802,13 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
   }
 }
 
+// A wave-uniform pointer to global memory, marked as such.
+template <typename T>
+__device__ __forceinline__ T* gptr(T* p) {
+  using G = __attribute__((address_space(1))) T;
+  return (T*)(G*)(uintptr_t)uni64((uint64_t)(uintptr_t)p);
+}
+
 // Batch b of the launch (b uniform). The argument copies of the first two
 // batches are read by selection, never by a dynamic index, which would move
 // the whole argument block to scratch.
@@ -770,16 +816,18 @@ __device__ __forceinline__ BatchArgs batch_at(const KArgs& A, uint32_t b) {
   BatchArgs B = A.batches ? A.batches[b] : (b ? A.b[1] : A.b[0]);
   // a descriptor read from global memory is wave-uniform, but the compiler
   // cannot tell: keep its fields in scalar registers so that addresses built
-  // from them (key tables above all) use scalar loads
-  B.buf = (const uint8_t*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.buf);
+  // from them (key tables above all) use scalar loads. The pointers are
+  // rebuilt as global-memory pointers so that accesses through them stay
+  // global loads and stores (generic ones would also count as LDS accesses).
+  B.buf = gptr(B.buf);
   B.buf_bytes = uni64(B.buf_bytes);
-  B.offsets = (const int64_t*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.offsets);
+  B.offsets = gptr(B.offsets);
   B.count = uni64s(B.count);
-  B.keys = (const void*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.keys);
-  B.out = (void*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.out);
+  B.keys = gptr(B.keys);
+  B.out = gptr(B.out);
   B.flags = uni(B.flags);
   B.wide = uni(B.wide);
-  B.slots = (Slot*)(uintptr_t)uni64((uint64_t)(uintptr_t)B.slots);
+  B.slots = gptr(B.slots);
   B.nslots = uni64(B.nslots);
   B.work0 = uni64(B.work0);
   B.work = uni64(B.work);
