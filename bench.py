@@ -235,6 +235,7 @@ def main():
     ap.add_argument("--g64", type=int, default=0, help="lanes per block, PM+64 (0: default)")
     ap.add_argument("--waves-per-cu", type=int, default=0, help="waves per CU (0: as many as stay resident)")
     ap.add_argument("--alpha", type=int, default=0, help="per-string work weight in bytes (0: default)")
+    ap.add_argument("--shares", type=int, default=0, help="shares of the work per wave (0: default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -263,15 +264,15 @@ def main():
     plan = pmp.Plan(0)
     plan.reserve(sum(rg.buf.size for rg in wl.batches), wl.count)
     stream = torch.cuda.current_stream()
-    manual = bool(args.g32 or args.g64 or args.waves_per_cu or args.alpha)
+    manual = bool(args.g32 or args.g64 or args.waves_per_cu or args.alpha or args.shares)
     if manual:
         if args.g32:
             plan.set_tile(False, args.g32)
         if args.g64:
             plan.set_tile(True, args.g64)
-        plan.tune(args.waves_per_cu, args.alpha, 0)
+        plan.tune(args.waves_per_cu, args.alpha, 0, args.shares)
         tuning = {"source": "command line", "g32": plan_g(args.g32), "g64": plan_g(args.g64, True),
-                  "alpha": args.alpha or 64, "waves_per_cu": args.waves_per_cu}
+                  "alpha": args.alpha or 64, "waves_per_cu": args.waves_per_cu, "shares_per_wave": args.shares or 1}
     else:  # the library's autotuner, on this workload, before the warm-up
         tuning = pmp.pmp_plan_autotune(plan, [b for b in batches if b is not None], stream=stream)
         tuning = {"source": "pmp_plan_autotune", **{k: (round(v, 4) if isinstance(v, float) else v)

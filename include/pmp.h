@@ -111,8 +111,11 @@ int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream);
 int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block);
 /* Launch shape: waves per CU (0 = as many as stay resident), the per-string
  * work weight alpha in byte equivalents used to split a batch between waves
- * (0 = keep), and the smallest share of work worth a wave (0 = keep). */
-int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes);
+ * (0 = keep), the smallest share of work worth a wave (0 = keep), and the
+ * number of shares each wave takes, spread over the batch (1..64, 0 = keep;
+ * more shares even out regions of the batch that cost more per byte, at a
+ * small search cost per share). */
+int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes, int shares_per_wave);
 
 /* ---------------------------------------------------------------------- */
 /* Hashing a batch (Algorithm 1 with Eq. (1) blocks, Sec. 4 byte padding,
@@ -185,15 +188,17 @@ int pmp_graph_destroy(pmp_graph* graph);
 
 /* Autotuner: times pmp_hash_many(plan, batches, nbatch, stream) over every
  * compiled lanes-per-block pair and per-string weight alpha in {32, 64, 128},
- * then over launch widths of 4, 12 and 16 waves per CU on the best of those,
- * leaves the fastest setting in the plan and reports it in *best (may be
- * NULL). The outputs are written by every timed launch (same values). The
- * stream is synchronized. */
+ * then over 1, 2 and 4 shares per wave, then over launch widths of 4, 12 and
+ * 16 waves per CU, each stage on the best of the one before; leaves the
+ * fastest setting in the plan and reports it in *best (may be NULL). The
+ * outputs are written by every timed launch (same values). The stream is
+ * synchronized. */
 typedef struct pmp_tuning {
-  int32_t g32, g64;     /* lanes per block, PM+32 / PM+64 */
-  uint32_t alpha;       /* per-string work weight, bytes */
-  int32_t waves_per_cu; /* 0: as many as stay resident */
-  float ms;             /* mean launch time of the chosen setting */
+  int32_t g32, g64;        /* lanes per block, PM+32 / PM+64 */
+  uint32_t alpha;          /* per-string work weight, bytes */
+  int32_t waves_per_cu;    /* 0: as many as stay resident */
+  int32_t shares_per_wave; /* shares of the work per wave */
+  float ms;                /* mean launch time of the chosen setting */
 } pmp_tuning;
 int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_stream_t stream,
                       pmp_tuning* best);

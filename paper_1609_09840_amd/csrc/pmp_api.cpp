@@ -63,6 +63,7 @@ struct pmp_plan {
   uint32_t alpha = 64;         // per-string work in byte equivalents
   uint64_t wave_bytes = 8192;  // smallest share of work worth a wave
   int waves_per_cu = 0;        // 0: as many as stay resident
+  int shares_per_wave = 1;     // shares of the work per wave (spread over the launch)
   int cus = 0;
   // descriptors of calls with more than two batches
   pmp::BatchArgs* desc_host = nullptr;  // pinned
@@ -241,8 +242,12 @@ int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, Prepared&
   if (waves < 1) waves = 1;
   if (waves > max_waves) waves = max_waves;
   P.a.total_waves = (uint32_t)waves;
+  // small launches keep one share per wave
+  uint64_t per_wave = (uint64_t)plan->shares_per_wave;
+  while (per_wave > 1 && work / (waves * per_wave) < plan->wave_bytes / 2) per_wave /= 2;
+  P.a.per_wave = (uint32_t)per_wave;
   P.a.total = work;
-  P.a.share = (work + waves - 1) / waves;
+  P.a.share = (work + waves * per_wave - 1) / (waves * per_wave);
   P.grid = (int)((waves + 3) / 4);
   return PMP_OK;
 }
@@ -445,12 +450,14 @@ int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block) {
   return PMP_OK;
 }
 
-int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes) {
-  if (!plan || waves_per_cu < 0 || waves_per_cu > 64) return fail(PMP_E_INVALID_ARG, "bad tuning values");
+int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes, int shares_per_wave) {
+  if (!plan || waves_per_cu < 0 || waves_per_cu > 64 || shares_per_wave < 0 || shares_per_wave > 64)
+    return fail(PMP_E_INVALID_ARG, "bad tuning values");
   std::lock_guard<std::mutex> lk(plan->mu);
   plan->waves_per_cu = waves_per_cu;
   if (alpha) plan->alpha = alpha;
   if (wave_bytes) plan->wave_bytes = wave_bytes;
+  if (shares_per_wave) plan->shares_per_wave = shares_per_wave;
   return PMP_OK;
 }
 
@@ -568,51 +575,44 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
     *ms /= reps;
     return PMP_OK;
   };
-  pmp_tuning cur{plan->g32, plan->g64, plan->alpha, plan->waves_per_cu, 0.f};
+  pmp_tuning cur{plan->g32, plan->g64, plan->alpha, plan->waves_per_cu, plan->shares_per_wave, 0.f};
   pmp_tuning top = cur;
   top.ms = 1e30f;
+  auto apply = [&](const pmp_tuning& t) {
+    std::lock_guard<std::mutex> lk(plan->mu);
+    plan->g32 = t.g32;
+    plan->g64 = t.g64;
+    plan->alpha = t.alpha;
+    plan->waves_per_cu = t.waves_per_cu;
+    plan->shares_per_wave = t.shares_per_wave;
+  };
+  auto trial = [&](pmp_tuning t) -> int {
+    apply(t);
+    float ms = 0;
+    const int rr = measure(&ms);
+    if (!rr && ms < top.ms) {
+      t.ms = ms;
+      top = t;
+    }
+    return rr;
+  };
   int pairs[16][2];
   const int np = pmp::batch_tile_pairs(pairs, 16);
   const uint32_t alphas[] = {32, 64, 128};
   int r = PMP_OK;
   for (int t = 0; t < np && !r; ++t)
-    for (uint32_t al : alphas) {
-      {
-        std::lock_guard<std::mutex> lk(plan->mu);
-        plan->g32 = pairs[t][0];
-        plan->g64 = pairs[t][1];
-        plan->alpha = al;
-        plan->waves_per_cu = 0;
-      }
-      float ms = 0;
-      r = measure(&ms);
-      if (r) break;
-      if (ms < top.ms) top = pmp_tuning{pairs[t][0], pairs[t][1], al, 0, ms};
-    }
-  if (!r) {  // then the launch width, on the best tiles
-    const int wpcs[] = {4, 12, 16};
-    for (int w : wpcs) {
-      {
-        std::lock_guard<std::mutex> lk(plan->mu);
-        plan->g32 = top.g32;
-        plan->g64 = top.g64;
-        plan->alpha = top.alpha;
-        plan->waves_per_cu = w;
-      }
-      float ms = 0;
-      r = measure(&ms);
-      if (r) break;
-      if (ms < top.ms) top = pmp_tuning{top.g32, top.g64, top.alpha, w, ms};
-    }
-  }
+    for (uint32_t al : alphas)
+      if (!r) r = trial(pmp_tuning{pairs[t][0], pairs[t][1], al, 0, 1, 0.f});
+  const int shares[] = {2, 4};
+  for (int sp : shares)
+    if (!r) r = trial(pmp_tuning{top.g32, top.g64, top.alpha, 0, sp, 0.f});
+  const int wpcs[] = {4, 12, 16};
+  for (int wv : wpcs)
+    if (!r) r = trial(pmp_tuning{top.g32, top.g64, top.alpha, wv, top.shares_per_wave, 0.f});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  std::lock_guard<std::mutex> lk(plan->mu);
   const pmp_tuning keep = r ? cur : top;
-  plan->g32 = keep.g32;
-  plan->g64 = keep.g64;
-  plan->alpha = keep.alpha;
-  plan->waves_per_cu = keep.waves_per_cu;
+  apply(keep);
   if (best) *best = keep;
   return r;
 }

@@ -40,8 +40,9 @@ struct BatchArgs {
 
 // The work of a launch is the sum over batches of alpha * count + buf_bytes:
 // string i of a batch starts at work position work0 + alpha * i + offsets[i]
-// (a byte of buffer and a string each count as work). Wave w takes
-// [w * share, (w + 1) * share) of it.
+// (a byte of buffer and a string each count as work). The work is cut into
+// per_wave * total_waves shares of `share` units; wave w takes shares w,
+// w + total_waves, w + 2 total_waves, ...
 struct KArgs {
   BatchArgs b[2];              // up to two batches travel in the arguments...
   const BatchArgs* batches;    // ...more come as a device array (else null)
@@ -49,8 +50,9 @@ struct KArgs {
   uint32_t alpha;        // per-string work in byte equivalents
   int32_t* status;       // device status word (STATUS_* bits)
   uint32_t total_waves;  // waves sharing the work
+  uint32_t per_wave;     // shares per wave
   uint64_t total;        // work of all batches
-  uint64_t share;        // work per wave
+  uint64_t share;        // work per share
 };
 
 // host side (pmp_api.cpp)

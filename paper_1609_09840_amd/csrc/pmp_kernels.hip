@@ -129,7 +129,7 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // MEDIUM_BLOCKS blocks, wholly in this wave's share) one per G-lane group;
 // longer strings, or strings cut by the share's ends, by the whole wave.
 constexpr uint32_t TINY_GROUPS = 16;
-constexpr int64_t MEDIUM_BLOCKS = 4;
+constexpr int64_t MEDIUM_BLOCKS = 16;
 
 // ---------------------------------------------------------------------------
 // Strings of at most TINY_GROUPS groups, one per lane, read from LDS.
@@ -664,6 +664,237 @@ __device__ void locate2(const BatchArgs& B, uint32_t alpha, uint64_t x0, uint64_
 
 // All blocks in [ps, pe) of one batch, 64 strings at a time.
 // Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
+// TINY_GROUPS groups). Their blocks form one task list (string by string, in
+// lane order); task t goes to G-lane group t mod (64 / G) at step
+// t / (64 / G), so every group has the same number of blocks whatever the
+// lengths. A block is summed by its group as in block_sum and folded
+// (Sec. 6.2, Algorithm 2); its field element goes to LDS. The next step's
+// block is loaded while the current one is summed. Then one lane per string
+// forms the level-2 value b_2 + sum_c a_{2,c} z_c (Eq. (1) on level 2) from
+// the stored elements. Strings whose tasks do not fit the LDS take a further
+// round. `med` marks lanes whose string (i, o0, len, C1) is medium; `zbuf`
+// and `tab` are the wave's stage and table.
+constexpr uint32_t MEDIUM_TASKS = STAGE_BYTES / 16;  // field elements held at once
+
+template <bool WIDE, int G>
+__device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* zbuf, uint32_t* tab, bool med,
+                               int64_t i, int64_t o0, int64_t len, int64_t C1) {
+  using T = Tr<WIDE>;
+  using Sum = typename T::Sum;
+  constexpr int W = T::W;
+  constexpr int CPS = 64 / G;
+  constexpr int64_t BW = BLOCK * W;
+  uint64_t todo = __ballot(med);
+  if (!todo) return;
+  const int lane = lane_id();
+  const int g = lane / G, j = lane % G;
+  const uint8_t* lo = B.buf;
+  const uint8_t* hi = B.buf + B.buf_bytes;
+  const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
+  const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
+  const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
+  uint64_t* zl = (uint64_t*)zbuf;  // task t: z.lo at 2t, z.hi at 2t + 1
+  const uint32_t nc = med ? (uint32_t)C1 : 0u;
+  uint64_t tot = 0;
+  const uint32_t t0 = (uint32_t)wave_excl_scan(nc, &tot);  // first task of this lane's string
+  uint32_t base = 0;
+  const uint8_t* s = B.buf + (med ? o0 : 0);
+  const uint32_t sh = (uint32_t)((uintptr_t)s & 3u);
+  const uint8_t* a4 = s - sh;
+  while (todo) {
+    const bool in = ((todo >> lane) & 1ull) && t0 + nc - base <= MEDIUM_TASKS;
+    const uint64_t pm = __ballot(in);
+    const uint32_t tr = wave_max(in ? t0 + nc - base : 0u);  // tasks of this round
+    if (in)
+      for (uint32_t c = 0; c < nc; ++c) tab[t0 - base + c] = (uint32_t)lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the block of task t, for this lane's group (every lane takes part in
+    // the shuffles: ds_bpermute reads 0 from a disabled source lane)
+    auto task = [&](uint32_t t, const uint8_t*& blk, uint32_t& bsh, int64_t& rem, uint32_t& bc) {
+      const bool v = t < tr;
+      const int src = v ? (int)tab[t] : lane;
+      const uint64_t sa = (uint64_t)__shfl((long long)(uint64_t)(uintptr_t)a4, src, 64);
+      const uint32_t ssh = (uint32_t)__shfl((int)sh, src, 64);
+      const int64_t sl = __shfl((long long)len, src, 64);
+      const uint32_t st = (uint32_t)__shfl((int)t0, src, 64);
+      bc = v ? t + base - st : 0u;  // block of its string
+      blk = v ? (const uint8_t*)(uintptr_t)(sa + (uint64_t)bc * BW) : safe;
+      bsh = v ? ssh : 0u;
+      rem = v ? sl - (int64_t)bc * BW : -(int64_t)BW - 64;  // invalid: everything masked
+    };
+    const uint32_t steps = (tr + CPS - 1) / CPS;
+    const uint8_t* nblk;
+    uint32_t nsh, nbc;
+    int64_t nrem;
+    task((uint32_t)g, nblk, nsh, nrem, nbc);
+    bool have = (uint32_t)g < tr && inside(nblk, BW + 4, lo, hi);
+    Pieces<WIDE, G> nxt;
+    block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh);
+    for (uint32_t st = 0; st < steps; ++st) {
+      asm volatile("" ::: "memory");  // keys stay in LDS
+      const Pieces<WIDE, G> cur = nxt;
+      const bool cur_loaded = have;
+      const uint32_t t = st * CPS + (uint32_t)g;
+      const bool act = t < tr;
+      const uint8_t* blk = nblk;
+      const uint32_t bsh = nsh;
+      const int64_t rem = nrem;
+      // the group's next task, loaded while this one is summed
+      task(t + CPS, nblk, nsh, nrem, nbc);
+      have = t + CPS < tr && inside(nblk, BW + 4, lo, hi);
+      block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh);
+      Sum bs;
+      if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, bsh, lk, act, rem, lo, hi);
+      else bs = block_sum<WIDE, G, true>(cur, j, bsh, lk, act, rem);
+      group_sum<G>(bs);
+      add_word(bs, b1);
+      const Fe z = reduce(bs);
+      if (act && j == 0) {
+        zl[2 * t] = z.lo;
+        zl[2 * t + 1] = z.hi;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // level 2, one lane per string
+    const uint32_t mc = wave_max(in ? nc : 0u);
+    Sum acc2;
+    zero(acc2);
+    Fe res = {0, 0};
+    const uint32_t tb = in ? t0 - base : 0u;
+    for (uint32_t c = 0; c < mc; ++c) {
+      const bool on = in && c < nc;
+      const Fe z = {on ? zl[2 * (tb + c)] : 0ull, on ? (uint32_t)zl[2 * (tb + c) + 1] : 0u};
+      if (c == 0) res = z;
+      mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
+    }
+    if (in) {
+      if (nc > 1) {
+        add_word(acc2, b2);
+        res = reduce(acc2);
+      }
+      store_out<WIDE>(B, i, res);
+    }
+    __builtin_amdgcn_wave_barrier();  // the table and the elements are read before the next round
+    todo &= ~pm;
+    base += tr;
+  }
+}
+
+// All blocks in [ps, pe) of one batch, 64 strings at a time.
+// Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
+// TINY_GROUPS groups), one string at a time per G-lane group: the k-th medium
+// string of the tile (in lane order) goes to group k mod (64 / G). Each group
+// walks the blocks of its strings one after another, the wave stepping all
+// groups together; a block is summed by its group as in block_sum, folded
+// (Sec. 6.2, Algorithm 2) and multiplied into the group's level-2 sum, and
+// the group's next block (of the same string or of its next one) is loaded
+// while the current one is summed, so the loads stay in flight across string
+// ends. `med` marks lanes whose string (i, o0, len, C1) is medium; `tab` is
+// 64 words of the wave's LDS.
+template <bool WIDE, int G>
+__device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint32_t* tab, bool med, int64_t i, int64_t o0,
+                               int64_t len, int64_t C1) {
+  using T = Tr<WIDE>;
+  using Sum = typename T::Sum;
+  constexpr int W = T::W;
+  constexpr int CPS = 64 / G;
+  constexpr int64_t BW = BLOCK * W;
+  const uint64_t m = __ballot(med);
+  if (!m) return;
+  const int lane = lane_id();
+  const int g = lane / G, j = lane % G;
+  const uint8_t* lo = B.buf;
+  const uint8_t* hi = B.buf + B.buf_bytes;
+  const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
+  const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
+  const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
+  // lane of the medium string of each rank
+  const uint32_t nmed = (uint32_t)__popcll(m);
+  const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  if (med) tab[rank] = (uint32_t)lane;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // the string of rank q, for this lane's group (every lane takes part in
+  // the shuffles: ds_bpermute reads 0 from a disabled source lane)
+  auto fetch = [&](uint32_t q, int64_t& si, const uint8_t*& a4, uint32_t& sh, int64_t& sl, int64_t& sc) {
+    const bool has = q < nmed;
+    const int src = has ? (int)tab[q] : lane;
+    const int64_t vi = __shfl((long long)i, src, 64);
+    const int64_t vo = __shfl((long long)o0, src, 64);
+    const int64_t vl = __shfl((long long)len, src, 64);
+    const int64_t vc = __shfl((long long)C1, src, 64);
+    si = vi;
+    sl = has ? vl : 0;
+    sc = has ? vc : 0;
+    const uint8_t* s = B.buf + (has ? vo : 0);
+    sh = (uint32_t)((uintptr_t)s & 3u);
+    a4 = s - sh;
+  };
+  auto plain = [&](const uint8_t* blk, bool valid) { return valid && inside(blk, BW + 4, lo, hi); };
+  uint32_t q = (uint32_t)g;
+  int64_t si, sl, sc;
+  const uint8_t* a4;
+  uint32_t sh;
+  fetch(q, si, a4, sh, sl, sc);
+  int64_t c = 0;  // block of the current string
+  Sum acc2;
+  zero(acc2);
+  Pieces<WIDE, G> nxt;
+  bool have = plain(a4, sc > 0);
+  block_loads<WIDE, G>(nxt, have ? a4 : safe, j, sh);
+  while (__ballot(sc > 0)) {
+    asm volatile("" ::: "memory");  // keys stay in LDS
+    const Pieces<WIDE, G> cur = nxt;
+    const bool cur_loaded = have;
+    const bool act = sc > 0;
+    const bool last = act && c + 1 >= sc;
+    // the group's next block: the next one of this string, or block 0 of its
+    // next string
+    int64_t si2 = si, sl2 = sl, sc2 = sc;
+    const uint8_t* a42 = a4;
+    uint32_t sh2 = sh;
+    if (__ballot(last)) fetch(q + (uint32_t)CPS, si2, a42, sh2, sl2, sc2);
+    const uint8_t* nblk = last ? a42 : a4 + (c + 1) * BW;
+    have = plain(nblk, act && (last ? sc2 > 0 : true));
+    block_loads<WIDE, G>(nxt, have ? nblk : safe, j, sh2);
+    // this block
+    const uint8_t* blk = act ? a4 + c * BW : safe;
+    const int64_t rem = sl - c * BW;
+    Sum bs;
+    if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
+    else bs = block_sum<WIDE, G, true>(cur, j, sh, lk, act, rem);
+    group_sum<G>(bs);
+    add_word(bs, b1);
+    const Fe z = reduce(bs);
+    if (act && sc > 1) mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
+    if (last) {
+      Fe res = z;
+      if (sc > 1) {
+        add_word(acc2, b2);
+        res = reduce(acc2);
+      }
+      if (j == 0) store_out<WIDE>(B, si, res);
+      zero(acc2);
+      q += (uint32_t)CPS;
+      si = si2;
+      sl = sl2;
+      sc = sc2;
+      a4 = a42;
+      sh = sh2;
+      c = 0;
+    } else if (act) {
+      ++c;
+    }
+  }
+}
+
+// All blocks in [ps, pe) of one batch, 64 strings at a time.
+// Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
 // TINY_GROUPS groups), one string per G-lane group: the CPS groups of the
 // wave walk their strings block by block together, each block summed by its
 // group as in block_sum, folded (Sec. 6.2, Algorithm 2) and multiplied into
@@ -782,7 +1013,7 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
     const bool lng = ok && !tiny && !med && lo_c < hi_c;
 
     short_strings<WIDE>(B, lk, stage, table, i, tiny, o0, len);
-    medium_strings<WIDE, G>(B, lk, med, i, o0, len, C1);
+    medium_strings<WIDE, G>(B, lk, stage, table, med, i, o0, len, C1);
 
     // the long strings, one at a time by the whole wave
     uint64_t m = __ballot(lng);
@@ -849,51 +1080,62 @@ __global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
   uint32_t* table = tables[threadIdx.x / 64];
   const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (w >= A.total_waves) return;
-  const uint64_t x0 = w * A.share < A.total ? w * A.share : A.total;
-  const uint64_t x1 = x0 + A.share < A.total ? x0 + A.share : A.total;
-  if (x0 >= x1) return;
   const uint32_t nb = A.nbatch;
-  // the batches that overlap [x0, x1), in order, 64 descriptors at a time
-  for (uint32_t base = 0; base < nb; base += 64) {
-    const uint32_t b = base + (uint32_t)lane;
-    uint64_t s0 = 0, sw = 0;
-    if (b < nb) {
-      if (A.batches) {
-        s0 = A.batches[b].work0;
-        sw = A.batches[b].work;
-      } else {
-        s0 = b ? A.b[1].work0 : A.b[0].work0;
-        sw = b ? A.b[1].work : A.b[0].work;
+  const void* staged = nullptr;  // key table now in lk
+  uint32_t staged_wide = 0;
+  // shares w, w + W, w + 2W, ... (W waves): a wave's work is spread over the
+  // launch, which evens out regions that cost more per unit of work
+  for (uint32_t k = 0; k < A.per_wave; ++k) {
+    const uint64_t sx = w + (uint64_t)k * A.total_waves;
+    const uint64_t x0 = sx * A.share < A.total ? sx * A.share : A.total;
+    const uint64_t x1 = x0 + A.share < A.total ? x0 + A.share : A.total;
+    if (x0 >= x1) break;  // later shares lie further on
+    // the batches that overlap [x0, x1), in order, 64 descriptors at a time
+    for (uint32_t base = 0; base < nb; base += 64) {
+      const uint32_t b = base + (uint32_t)lane;
+      uint64_t s0 = 0, sw = 0;
+      if (b < nb) {
+        if (A.batches) {
+          s0 = A.batches[b].work0;
+          sw = A.batches[b].work;
+        } else {
+          s0 = b ? A.b[1].work0 : A.b[0].work0;
+          sw = b ? A.b[1].work : A.b[0].work;
+        }
       }
-    }
-    uint64_t m = __ballot(b < nb && sw > 0 && s0 < x1 && s0 + sw > x0);
-    const bool past = __ballot(b < nb && s0 >= x1) != 0;  // later chunks start past x1 too
-    while (m) {
-      const int l = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      const BatchArgs B = batch_at(A, base + (uint32_t)l);
-      const uint64_t lo = x0 > B.work0 ? x0 - B.work0 : 0;
-      const uint64_t hi = x1 < B.work0 + B.work ? x1 - B.work0 : B.work;
-      // this batch's keys into the wave's LDS region
+      uint64_t m = __ballot(b < nb && sw > 0 && s0 < x1 && s0 + sw > x0);
+      const bool past = __ballot(b < nb && s0 >= x1) != 0;  // later chunks start past x1 too
+      while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const BatchArgs B = batch_at(A, base + (uint32_t)l);
+        const uint64_t lo = x0 > B.work0 ? x0 - B.work0 : 0;
+        const uint64_t hi = x1 < B.work0 + B.work ? x1 - B.work0 : B.work;
+        if (B.keys != staged || B.wide != staged_wide) {
+          // this batch's keys into the wave's LDS region
+          __builtin_amdgcn_wave_barrier();  // all lanes done with the previous keys
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = lane + 64 * k;
-        lk[e] = B.wide ? ((const uint64_t*)B.keys)[e] : ((const uint32_t*)B.keys)[e];
+          for (int q = 0; q < 4; ++q) {
+            const int e = lane + 64 * q;
+            lk[e] = B.wide ? ((const uint64_t*)B.keys)[e] : ((const uint32_t*)B.keys)[e];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          staged = B.keys;
+          staged_wide = B.wide;
+        }
+        Pos ps, pe;
+        if (B.wide) {
+          locate2<8>(B, A.alpha, lo, hi, ps, pe);
+          run_range<true, G64>(A, B, lk, stage, table, ps, pe);
+        } else {
+          locate2<4>(B, A.alpha, lo, hi, ps, pe);
+          run_range<false, G32>(A, B, lk, stage, table, ps, pe);
+        }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      Pos ps, pe;
-      if (B.wide) {
-        locate2<8>(B, A.alpha, lo, hi, ps, pe);
-        run_range<true, G64>(A, B, lk, stage, table, ps, pe);
-      } else {
-        locate2<4>(B, A.alpha, lo, hi, ps, pe);
-        run_range<false, G32>(A, B, lk, stage, table, ps, pe);
-      }
-      __builtin_amdgcn_wave_barrier();  // all lanes done with the keys before the next batch's
+      if (past) break;
     }
-    if (past) break;
   }
 }
 

@@ -80,6 +80,7 @@ class pmp_tuning(ctypes.Structure):
         ("g64", ctypes.c_int32),
         ("alpha", ctypes.c_uint32),
         ("waves_per_cu", ctypes.c_int32),
+        ("shares_per_wave", ctypes.c_int32),
         ("ms", ctypes.c_float),
     ]
 
@@ -119,7 +120,7 @@ def _load():
         "pmp_plan_reserve": [vp, u64, i64],
         "pmp_plan_status": [vp, vp],
         "pmp_plan_set_tile": [vp, i32, i32],
-        "pmp_plan_tune": [vp, i32, u32, u64],
+        "pmp_plan_tune": [vp, i32, u32, u64, i32],
         "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
@@ -222,8 +223,8 @@ class Plan:
     def set_tile(self, wide: bool, lanes_per_block: int):
         _check(_lib.pmp_plan_set_tile(self.handle, int(wide), lanes_per_block))
 
-    def tune(self, waves_per_cu: int = 0, alpha: int = 0, wave_bytes: int = 0):
-        _check(_lib.pmp_plan_tune(self.handle, waves_per_cu, alpha, wave_bytes))
+    def tune(self, waves_per_cu: int = 0, alpha: int = 0, wave_bytes: int = 0, shares_per_wave: int = 0):
+        _check(_lib.pmp_plan_tune(self.handle, waves_per_cu, alpha, wave_bytes, shares_per_wave))
 
     def status(self, stream=None) -> int:
         return _lib.pmp_plan_status(self.handle, _stream(stream))

@@ -267,3 +267,26 @@ def test_autotune_keeps_results():
     for rg, flags, buf, off, out in keep:
         assert U.first_mismatch(U.as_u64(out.cpu().numpy()), oracle_of(rg, flags)) is None
     plan.close()
+
+
+@pytest.mark.parametrize("shares", [2, 4, 16])
+def test_shares_per_wave(shares):
+    """Work spread over several shares per wave gives the same outputs."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    lens, wide = W.c4_lengths(6000, seed=951)
+    specs = [(W.from_lengths(lens[~wide], 952, False), 0), (W.from_lengths(lens[wide], 953, True), 2)]
+    k32 = U.to_dev_keys(U.keys_for(False, W.KEY_SEED32))
+    k64 = U.to_dev_keys(U.keys_for(True, W.KEY_SEED64))
+    keep, batches = _batches_for(specs, k32, k64)
+    plan = pmp.Plan(0)
+    plan.tune(0, 0, 1024, shares)
+    say(f"case shares={shares}")
+    pmp.pmp_hash_many(batches, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == pmp.PMP_OK
+    for rg, flags, buf, off, out in keep:
+        assert U.first_mismatch(U.as_u64(out.cpu().numpy()), oracle_of(rg, flags)) is None
+    plan.close()
