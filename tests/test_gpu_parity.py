@@ -288,3 +288,31 @@ def test_fold_matches_exact_mod(wide):
         S = a + (b << n) + (c << (2 * n))
         got = (int(zz[2 * idx]) + (int(zz[2 * idx + 1]) << 64)) if wide else int(zz[idx])
         assert got == S % p, (a, b, c, got, S % p)
+
+
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("lead", [0, 3])
+def test_stage_overflow_passes(wide, lead):
+    """Runs of the longest one-lane strings (their chunks overflow the LDS
+    stage, so a tile takes several passes) and of the longest medium strings
+    (their block tasks overflow the LDS, several rounds), at both ends of the
+    length classes."""
+    Wb = 8 if wide else 4
+    blk = 128 * Wb
+    rng = np.random.default_rng(61 + lead)
+    tiny = rng.integers(236, 256, size=300)                    # 15..16 groups of 16 bytes
+    med = rng.integers(15 * blk + 1, 16 * blk - Wb, size=200)  # 16 blocks each
+    mixed = np.concatenate([tiny[:100], med[:100], tiny[100:], med[100:], rng.integers(0, 16 * blk, size=300)])
+    from paper_1609_09840_amd import pmp
+
+    plan = pmp.Plan(0)
+    plan.tune(0, 0, 1 << 26, 1)  # few waves: every tile holds 64 such strings
+    keys = U.keys_for(wide, 63)
+    for name, lengths in (("tiny", tiny), ("medium", med), ("mixed", mixed)):
+        rg = W.from_lengths(lengths, 62 + lead, wide, lead=lead)
+        say(f"case stage-{name}: wide={wide} count={rg.count} bytes={rg.nbytes}")
+        got = U.gpu_hash(rg, keys, 0, plan=plan)
+        want = U.oracle_hash(rg, keys, 0)
+        assert U.first_mismatch(got, want) is None, (name, U.first_mismatch(got, want))
+    assert plan.status() == pmp.PMP_OK
+    plan.close()
