@@ -60,7 +60,7 @@ struct pmp_plan {
   pmp::Slot* slots = nullptr;  // device
   uint64_t nslots = 0;
   int g32 = 8, g64 = 16;
-  uint32_t alpha = 64;         // per-string work in byte equivalents
+  uint32_t alpha = 1024;       // per-string work in byte equivalents
   uint64_t wave_bytes = 8192;  // smallest share of work worth a wave
   int waves_per_cu = 0;        // 0: as many as stay resident
   int shares_per_wave = 1;     // shares of the work per wave (spread over the launch)
@@ -598,7 +598,7 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
   };
   int pairs[16][2];
   const int np = pmp::batch_tile_pairs(pairs, 16);
-  const uint32_t alphas[] = {32, 64, 128};
+  const uint32_t alphas[] = {128, 512, 1024, 2048};
   int r = PMP_OK;
   for (int t = 0; t < np && !r; ++t)
     for (uint32_t al : alphas)
