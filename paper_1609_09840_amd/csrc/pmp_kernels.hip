@@ -244,11 +244,17 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
     zero(acc);
     P64 p;
     zero(p);
+    constexpr int KPG = WIDE ? 2 : 4;  // keys per group
     for (uint32_t g = 0; g < maxg; ++g) {
       const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
       uint32_t d[5];
+      uint64_t kk[KPG];
 #pragma unroll
       for (int u = 0; u < 5; ++u) d[u] = q[u];
+#pragma unroll
+      for (int u = 0; u < KPG; ++u) kk[u] = lk[KPG * g + u];  // level-1 keys, staged in LDS
+      // every LDS read of the group is issued before its arithmetic
+      __builtin_amdgcn_sched_barrier(0);
       uint32_t x[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -256,11 +262,9 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
         x[u] = 16 * g + 4 * u < pe ? v : 0u;
       }
       if constexpr (WIDE) {
-        const uint64_t* kk = lk + 2 * g;  // level-1 keys, staged in LDS
         mac64_sv(p, kk[0], x[0], x[1]);
         mac64_sv(p, kk[1], x[2], x[3]);
       } else {
-        const uint64_t* kk = lk + 4 * g;
 #pragma unroll
         for (int u = 0; u < 4; ++u) mac_sv(acc.lo, acc.hi, (uint32_t)kk[u], x[u]);
       }
@@ -662,18 +666,18 @@ __device__ void locate2(const BatchArgs& B, uint32_t alpha, uint64_t x0, uint64_
   p1 = finish(x1, i1, 1);
 }
 
-// All blocks in [ps, pe) of one batch, 64 strings at a time.
 // Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
-// TINY_GROUPS groups). Their blocks form one task list (string by string, in
-// lane order); task t goes to G-lane group t mod (64 / G) at step
-// t / (64 / G), so every group has the same number of blocks whatever the
-// lengths. A block is summed by its group as in block_sum and folded
-// (Sec. 6.2, Algorithm 2); its field element goes to LDS. The next step's
-// block is loaded while the current one is summed. Then one lane per string
-// forms the level-2 value b_2 + sum_c a_{2,c} z_c (Eq. (1) on level 2) from
-// the stored elements. Strings whose tasks do not fit the LDS take a further
-// round. `med` marks lanes whose string (i, o0, len, C1) is medium; `zbuf`
-// and `tab` are the wave's stage and table.
+// TINY_GROUPS groups). Their blocks form one task list: first every block but
+// the last of each string (all of them full, summed without masks), then the
+// last blocks (masked to the padded string of Sec. 4). Task t goes to G-lane
+// group t mod (64 / G) at step t / (64 / G), so every group has the same
+// number of blocks whatever the lengths. A block is summed by its group as in
+// block_sum and folded (Sec. 6.2, Algorithm 2); its field element goes to
+// LDS. The next step's block is loaded while the current one is summed. Then
+// one lane per string forms the level-2 value b_2 + sum_c a_{2,c} z_c (Eq. (1)
+// on level 2) from the stored elements. Strings whose tasks do not fit the LDS
+// take a further round. `med` marks lanes whose string (i, o0, len, C1) is
+// medium; `zbuf` and `tab` are the wave's stage and table.
 constexpr uint32_t MEDIUM_TASKS = STAGE_BYTES / 16;  // field elements held at once
 
 template <bool WIDE, int G>
@@ -693,42 +697,84 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
   const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
   const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
   const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
+  uint64_t ntask = 0;
+  (void)wave_excl_scan(med ? (uint64_t)C1 : 0ull, &ntask);
+  const uint32_t nmed = (uint32_t)__popcll(todo);
+  if (ntask == nmed && nmed <= (uint32_t)CPS) {
+    // a few single-block strings: one per group, no task list to build
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(todo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
+    if (med) tab[rank] = (uint32_t)lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool act = (uint32_t)g < nmed;
+    const int src = act ? (int)tab[g] : lane;  // every lane takes part in the shuffles
+    const int64_t si = __shfl((long long)i, src, 64);
+    const int64_t so = __shfl((long long)o0, src, 64);
+    const int64_t sl = __shfl((long long)len, src, 64);
+    const uint8_t* sp = B.buf + (act ? so : 0);
+    const uint32_t ssh = (uint32_t)((uintptr_t)sp & 3u);
+    const uint8_t* blk = act ? sp - ssh : safe;
+    Sum bs;
+    if (__ballot(act && !inside(blk, BW + 4, lo, hi))) {
+      bs = block_guarded<WIDE, G>(blk, j, ssh, lk, act, sl, lo, hi);
+    } else {
+      Pieces<WIDE, G> P;
+      block_loads<WIDE, G>(P, blk, j, ssh);
+      bs = block_sum<WIDE, G, true>(P, j, ssh, lk, act, sl);
+    }
+    group_sum<G>(bs);
+    add_word(bs, b1);
+    const Fe z = reduce(bs);
+    if (act && j == 0) store_out<WIDE>(B, si, z);
+    __builtin_amdgcn_wave_barrier();  // the table is read before it is used again
+    return;
+  }
   uint64_t* zl = (uint64_t*)zbuf;  // task t: z.lo at 2t, z.hi at 2t + 1
   const uint32_t nc = med ? (uint32_t)C1 : 0u;
   uint64_t tot = 0;
-  const uint32_t t0 = (uint32_t)wave_excl_scan(nc, &tot);  // first task of this lane's string
+  const uint32_t c0 = (uint32_t)wave_excl_scan(nc, &tot);  // tasks before this lane's string
   uint32_t base = 0;
   const uint8_t* s = B.buf + (med ? o0 : 0);
   const uint32_t sh = (uint32_t)((uintptr_t)s & 3u);
   const uint8_t* a4 = s - sh;
   while (todo) {
-    const bool in = ((todo >> lane) & 1ull) && t0 + nc - base <= MEDIUM_TASKS;
+    const bool in = ((todo >> lane) & 1ull) && c0 + nc - base <= MEDIUM_TASKS;
     const uint64_t pm = __ballot(in);
-    const uint32_t tr = wave_max(in ? t0 + nc - base : 0u);  // tasks of this round
-    if (in)
-      for (uint32_t c = 0; c < nc; ++c) tab[t0 - base + c] = (uint32_t)lane;
+    uint64_t nfull = 0, nlast = 0;
+    const uint32_t f0 = (uint32_t)wave_excl_scan(in ? nc - 1 : 0u, &nfull);  // this string's full blocks
+    const uint32_t l0 = (uint32_t)wave_excl_scan(in ? 1u : 0u, &nlast);       // ... and its last one
+    const uint32_t nf = (uint32_t)nfull;
+    const uint32_t tr = nf + (uint32_t)nlast;  // tasks of this round
+    const uint32_t tlast = nf + l0;            // task of this string's last block
+    if (in) {
+      for (uint32_t c = 0; c + 1 < nc; ++c) tab[f0 + c] = (uint32_t)lane;
+      tab[tlast] = (uint32_t)lane;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the block of task t, for this lane's group (every lane takes part in
     // the shuffles: ds_bpermute reads 0 from a disabled source lane)
-    auto task = [&](uint32_t t, const uint8_t*& blk, uint32_t& bsh, int64_t& rem, uint32_t& bc) {
+    auto task = [&](uint32_t t, const uint8_t*& blk, uint32_t& bsh, int64_t& rem) {
       const bool v = t < tr;
       const int src = v ? (int)tab[t] : lane;
       const uint64_t sa = (uint64_t)__shfl((long long)(uint64_t)(uintptr_t)a4, src, 64);
       const uint32_t ssh = (uint32_t)__shfl((int)sh, src, 64);
       const int64_t sl = __shfl((long long)len, src, 64);
-      const uint32_t st = (uint32_t)__shfl((int)t0, src, 64);
-      bc = v ? t + base - st : 0u;  // block of its string
+      const uint32_t sf = (uint32_t)__shfl((int)f0, src, 64);
+      const uint32_t sn = (uint32_t)__shfl((int)nc, src, 64);
+      const uint32_t bc = t < nf ? t - sf : sn - 1;  // block of its string
       blk = v ? (const uint8_t*)(uintptr_t)(sa + (uint64_t)bc * BW) : safe;
       bsh = v ? ssh : 0u;
       rem = v ? sl - (int64_t)bc * BW : -(int64_t)BW - 64;  // invalid: everything masked
     };
     const uint32_t steps = (tr + CPS - 1) / CPS;
     const uint8_t* nblk;
-    uint32_t nsh, nbc;
+    uint32_t nsh;
     int64_t nrem;
-    task((uint32_t)g, nblk, nsh, nrem, nbc);
+    task((uint32_t)g, nblk, nsh, nrem);
     bool have = (uint32_t)g < tr && inside(nblk, BW + 4, lo, hi);
     Pieces<WIDE, G> nxt;
     block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh);
@@ -738,15 +784,17 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       const bool cur_loaded = have;
       const uint32_t t = st * CPS + (uint32_t)g;
       const bool act = t < tr;
+      const bool full = (st + 1) * CPS <= nf;  // uniform: every block of this step is full
       const uint8_t* blk = nblk;
       const uint32_t bsh = nsh;
       const int64_t rem = nrem;
       // the group's next task, loaded while this one is summed
-      task(t + CPS, nblk, nsh, nrem, nbc);
+      task(t + CPS, nblk, nsh, nrem);
       have = t + CPS < tr && inside(nblk, BW + 4, lo, hi);
       block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh);
       Sum bs;
       if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, bsh, lk, act, rem, lo, hi);
+      else if (full) bs = block_sum<WIDE, G, false>(cur, j, bsh, lk, true, 0);
       else bs = block_sum<WIDE, G, true>(cur, j, bsh, lk, act, rem);
       group_sum<G>(bs);
       add_word(bs, b1);
@@ -764,10 +812,10 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     Sum acc2;
     zero(acc2);
     Fe res = {0, 0};
-    const uint32_t tb = in ? t0 - base : 0u;
     for (uint32_t c = 0; c < mc; ++c) {
       const bool on = in && c < nc;
-      const Fe z = {on ? zl[2 * (tb + c)] : 0ull, on ? (uint32_t)zl[2 * (tb + c) + 1] : 0u};
+      const uint32_t tk = c + 1 < nc ? f0 + c : tlast;
+      const Fe z = {on ? zl[2 * tk] : 0ull, on ? (uint32_t)zl[2 * tk + 1] : 0u};
       if (c == 0) res = z;
       mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
     }
@@ -781,199 +829,6 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     __builtin_amdgcn_wave_barrier();  // the table and the elements are read before the next round
     todo &= ~pm;
     base += tr;
-  }
-}
-
-// All blocks in [ps, pe) of one batch, 64 strings at a time.
-// Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
-// TINY_GROUPS groups), one string at a time per G-lane group: the k-th medium
-// string of the tile (in lane order) goes to group k mod (64 / G). Each group
-// walks the blocks of its strings one after another, the wave stepping all
-// groups together; a block is summed by its group as in block_sum, folded
-// (Sec. 6.2, Algorithm 2) and multiplied into the group's level-2 sum, and
-// the group's next block (of the same string or of its next one) is loaded
-// while the current one is summed, so the loads stay in flight across string
-// ends. `med` marks lanes whose string (i, o0, len, C1) is medium; `tab` is
-// 64 words of the wave's LDS.
-template <bool WIDE, int G>
-__device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint32_t* tab, bool med, int64_t i, int64_t o0,
-                               int64_t len, int64_t C1) {
-  using T = Tr<WIDE>;
-  using Sum = typename T::Sum;
-  constexpr int W = T::W;
-  constexpr int CPS = 64 / G;
-  constexpr int64_t BW = BLOCK * W;
-  const uint64_t m = __ballot(med);
-  if (!m) return;
-  const int lane = lane_id();
-  const int g = lane / G, j = lane % G;
-  const uint8_t* lo = B.buf;
-  const uint8_t* hi = B.buf + B.buf_bytes;
-  const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
-  const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
-  const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
-  // lane of the medium string of each rank
-  const uint32_t nmed = (uint32_t)__popcll(m);
-  const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-  if (med) tab[rank] = (uint32_t)lane;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // the string of rank q, for this lane's group (every lane takes part in
-  // the shuffles: ds_bpermute reads 0 from a disabled source lane)
-  auto fetch = [&](uint32_t q, int64_t& si, const uint8_t*& a4, uint32_t& sh, int64_t& sl, int64_t& sc) {
-    const bool has = q < nmed;
-    const int src = has ? (int)tab[q] : lane;
-    const int64_t vi = __shfl((long long)i, src, 64);
-    const int64_t vo = __shfl((long long)o0, src, 64);
-    const int64_t vl = __shfl((long long)len, src, 64);
-    const int64_t vc = __shfl((long long)C1, src, 64);
-    si = vi;
-    sl = has ? vl : 0;
-    sc = has ? vc : 0;
-    const uint8_t* s = B.buf + (has ? vo : 0);
-    sh = (uint32_t)((uintptr_t)s & 3u);
-    a4 = s - sh;
-  };
-  auto plain = [&](const uint8_t* blk, bool valid) { return valid && inside(blk, BW + 4, lo, hi); };
-  uint32_t q = (uint32_t)g;
-  int64_t si, sl, sc;
-  const uint8_t* a4;
-  uint32_t sh;
-  fetch(q, si, a4, sh, sl, sc);
-  int64_t c = 0;  // block of the current string
-  Sum acc2;
-  zero(acc2);
-  Pieces<WIDE, G> nxt;
-  bool have = plain(a4, sc > 0);
-  block_loads<WIDE, G>(nxt, have ? a4 : safe, j, sh);
-  while (__ballot(sc > 0)) {
-    asm volatile("" ::: "memory");  // keys stay in LDS
-    const Pieces<WIDE, G> cur = nxt;
-    const bool cur_loaded = have;
-    const bool act = sc > 0;
-    const bool last = act && c + 1 >= sc;
-    // the group's next block: the next one of this string, or block 0 of its
-    // next string
-    int64_t si2 = si, sl2 = sl, sc2 = sc;
-    const uint8_t* a42 = a4;
-    uint32_t sh2 = sh;
-    if (__ballot(last)) fetch(q + (uint32_t)CPS, si2, a42, sh2, sl2, sc2);
-    const uint8_t* nblk = last ? a42 : a4 + (c + 1) * BW;
-    have = plain(nblk, act && (last ? sc2 > 0 : true));
-    block_loads<WIDE, G>(nxt, have ? nblk : safe, j, sh2);
-    // this block
-    const uint8_t* blk = act ? a4 + c * BW : safe;
-    const int64_t rem = sl - c * BW;
-    Sum bs;
-    if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
-    else bs = block_sum<WIDE, G, true>(cur, j, sh, lk, act, rem);
-    group_sum<G>(bs);
-    add_word(bs, b1);
-    const Fe z = reduce(bs);
-    if (act && sc > 1) mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
-    if (last) {
-      Fe res = z;
-      if (sc > 1) {
-        add_word(acc2, b2);
-        res = reduce(acc2);
-      }
-      if (j == 0) store_out<WIDE>(B, si, res);
-      zero(acc2);
-      q += (uint32_t)CPS;
-      si = si2;
-      sl = sl2;
-      sc = sc2;
-      a4 = a42;
-      sh = sh2;
-      c = 0;
-    } else if (act) {
-      ++c;
-    }
-  }
-}
-
-// All blocks in [ps, pe) of one batch, 64 strings at a time.
-// Medium strings (2..MEDIUM_BLOCKS blocks, or one block of more than
-// TINY_GROUPS groups), one string per G-lane group: the CPS groups of the
-// wave walk their strings block by block together, each block summed by its
-// group as in block_sum, folded (Sec. 6.2, Algorithm 2) and multiplied into
-// the group's own level-2 sum; no wave-wide reduction is needed. `med`
-// marks lanes whose string (i, o0, len, C1) is medium.
-template <bool WIDE, int G>
-__device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, bool med, int64_t i, int64_t o0, int64_t len,
-                               int64_t C1) {
-  using T = Tr<WIDE>;
-  using Sum = typename T::Sum;
-  constexpr int W = T::W;
-  constexpr int CPS = 64 / G;
-  const int lane = lane_id();
-  const int g = lane / G, j = lane % G;
-  const uint8_t* lo = B.buf;
-  const uint8_t* hi = B.buf + B.buf_bytes;
-  const uint8_t* safe = (const uint8_t*)B.keys;  // readable: 128 W + 16 bytes and more
-  const uint64_t b1 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK];
-  const uint64_t b2 = (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK + 1];
-  uint64_t m = __ballot(med);
-  while (m) {
-    // the next CPS medium strings, one per group
-    int own = 64;
-#pragma unroll
-    for (int k = 0; k < CPS; ++k) {
-      const int l = m ? __ffsll((unsigned long long)m) - 1 : 64;
-      if (m) m &= m - 1;
-      if (g == k) own = l;
-    }
-    const bool gact = own < 64;
-    const int src = gact ? own : lane;
-    // shuffles with every lane active (ds_bpermute reads 0 from a disabled
-    // source lane), selections afterwards
-    const int64_t si = __shfl((long long)i, src, 64);
-    const int64_t so = __shfl((long long)o0, src, 64);
-    const int64_t len_s = __shfl((long long)len, src, 64);
-    const int64_t c1_s = __shfl((long long)C1, src, 64);
-    const int64_t sl = gact ? len_s : 0;
-    const int64_t sc = gact ? c1_s : 0;
-    const uint8_t* s = B.buf + so;
-    const uint32_t sh = (uint32_t)((uintptr_t)s & 3u);
-    const uint8_t* a4 = s - sh;
-    const uint32_t nsteps = wave_max((uint32_t)sc);
-    Sum acc2;
-    zero(acc2);
-    Fe res = {0, 0};
-    // block c of the group's string is read with plain loads when it lies in
-    // the buffer; block c + 1 is loaded while block c is summed
-    auto plain = [&](uint32_t c) {
-      return (int64_t)c < sc && inside(a4 + (int64_t)c * (BLOCK * W), BLOCK * W + 4, lo, hi);
-    };
-    Pieces<WIDE, G> nxt;
-    bool have = plain(0);
-    block_loads<WIDE, G>(nxt, have ? a4 : safe, j, sh);
-    for (uint32_t c = 0; c < nsteps; ++c) {
-      asm volatile("" ::: "memory");  // keys stay in LDS
-      const Pieces<WIDE, G> cur = nxt;
-      const bool cur_loaded = have;
-      have = plain(c + 1);
-      block_loads<WIDE, G>(nxt, have ? a4 + (int64_t)(c + 1) * (BLOCK * W) : safe, j, sh);
-      const bool act = (int64_t)c < sc;
-      const uint8_t* blk = act ? a4 + (int64_t)c * (BLOCK * W) : safe;
-      const int64_t rem = sl - (int64_t)c * (BLOCK * W);
-      Sum bs;
-      if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, sh, lk, act, rem, lo, hi);
-      else bs = block_sum<WIDE, G, true>(cur, j, sh, lk, act, rem);
-      group_sum<G>(bs);
-      add_word(bs, b1);
-      const Fe z = reduce(bs);
-      if (act) {
-        if (sc == 1) res = z;
-        else mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
-      }
-    }
-    if (sc > 1) {
-      add_word(acc2, b2);
-      res = reduce(acc2);
-    }
-    if (gact && j == 0) store_out<WIDE>(B, si, res);
   }
 }
 
@@ -1066,7 +921,7 @@ __device__ __forceinline__ BatchArgs batch_at(const KArgs& A, uint32_t b) {
 }
 
 template <int G32, int G64>
-__global__ __launch_bounds__(256) void batch_kernel(KArgs A) {
+__global__ __launch_bounds__(256, 2) void batch_kernel(KArgs A) {
   // each wave keeps the level-1 and level-2 keys of the batch it works on in
   // its own LDS region, as 64-bit words
   __shared__ uint64_t lkeys[4][2 * BLOCK];
