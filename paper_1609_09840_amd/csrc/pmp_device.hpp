@@ -124,10 +124,13 @@ __device__ __forceinline__ Fe fold32(uint32_t w0, uint32_t w1, uint32_t w2) {
   uint32_t u0 = (uint32_t)kw1, u1 = (uint32_t)(kw1 >> 32);
   uint64_t v = (uint64_t)w0 + (uint64_t)(K32 * K32) * w2 + (uint64_t)K32 * u1 + ((1ull << 32) + K32 - u0);
   uint32_t v0 = (uint32_t)v, v1 = (uint32_t)(v >> 32);
-  uint64_t z;
-  if ((uint64_t)K32 * v1 <= v0) z = v0 - K32 * v1;
-  else if (v1 == 1) z = (uint64_t)v0 + (1ull << 32);
-  else z = (1ull << 32) - K32 + v0;
+  // Algorithm 2 (corrected), without branches: v1 <= 2, so the result is
+  // v0 - k v1 when that is not negative, else 2^32 + v0 (v1 = 1) or
+  // 2^32 - k + v0 (v1 = 2)
+  const uint32_t kv1 = K32 * v1;
+  const bool ge = kv1 <= v0;
+  const uint64_t wrap = (1ull << 32) + (uint64_t)v0 - (v1 == 1 ? 0u : K32);
+  const uint64_t z = ge ? (uint64_t)(v0 - kv1) : wrap;
   Fe r;
   r.lo = (uint32_t)z;
   r.hi = (uint32_t)(z >> 32);
@@ -142,18 +145,17 @@ __device__ __forceinline__ Fe fold64(uint64_t w0, uint64_t w1, uint32_t w2) {
   u128 v = (u128)w0 + (u128)(K64 * K64) * w2 + (u128)K64 * u1 + (((u128)1 << 64) + K64 - u0);
   uint64_t v0 = (uint64_t)v;
   uint32_t v1 = (uint32_t)(v >> 64);
+  // Algorithm 2 (corrected), without branches (v1 <= 2): v0 - k v1 when that
+  // is not negative, else 2^64 + v0 (v1 = 1) or 2^64 - k + v0 (v1 = 2)
+  const uint64_t kv1 = K64 * (uint64_t)v1;
+  const bool ge = kv1 <= v0;
+  const uint64_t sub = v1 == 1 ? 0ull : K64;
+  // 2^64 + v0 - sub: below 2^65; its high word is 0 when v0 < sub
+  const uint64_t wlo = v0 - sub;
+  const uint32_t whi = v0 >= sub ? 1u : 0u;
   Fe r;
-  if (K64 * v1 <= v0) {
-    r.lo = v0 - K64 * v1;
-    r.hi = 0;
-  } else if (v1 == 1) {
-    r.lo = v0;
-    r.hi = 1;
-  } else {
-    u128 z = ((u128)1 << 64) - K64 + v0;
-    r.lo = (uint64_t)z;
-    r.hi = (uint32_t)(z >> 64);
-  }
+  r.lo = ge ? v0 - kv1 : wlo;
+  r.hi = ge ? 0u : whi;
   return r;
 }
 __device__ __forceinline__ Fe reduce(const S64& s) { return fold64(s.w0, s.w1, s.w2); }

@@ -129,7 +129,7 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // MEDIUM_BLOCKS blocks, wholly in this wave's share) one per G-lane group;
 // longer strings, or strings cut by the share's ends, by the whole wave.
 constexpr uint32_t TINY_GROUPS = 16;
-constexpr int64_t MEDIUM_BLOCKS = 16;
+constexpr int64_t MEDIUM_BLOCKS = 32;
 
 // ---------------------------------------------------------------------------
 // Strings of at most TINY_GROUPS groups, one per lane, read from LDS.
