@@ -181,7 +181,9 @@ int pmp_hash_many(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_
  * offsets, keys and outputs are read at each replay, so new data in the same
  * buffers is hashed by the next replay. The plan must not be used by other
  * calls while a replay runs, and must outlive the graph. Creation allocates
- * (workspace, descriptors); replays do not. */
+ * (workspace, descriptors); replays do not. Later calls on the plan that
+ * need a larger workspace allocate a new one and keep the one the graphs
+ * use until the plan's last graph is destroyed. */
 typedef struct pmp_graph pmp_graph;
 int pmp_graph_create(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, pmp_graph** graph_out);
 int pmp_graph_launch(pmp_graph* graph, pmp_stream_t stream);

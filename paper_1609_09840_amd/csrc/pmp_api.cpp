@@ -70,6 +70,10 @@ struct pmp_plan {
   pmp::BatchArgs* desc_dev = nullptr;
   int desc_cap = 0;
   hipEvent_t desc_copied = nullptr;  // the last descriptor upload
+  // captured graphs hold workspace pointers: while any exist, workspace that
+  // grows is kept here instead of freed (freed with the last graph or the plan)
+  int graphs = 0;
+  std::vector<void*> retired;
   std::mutex mu;
 };
 
@@ -95,13 +99,24 @@ int plan_init(pmp_plan* p, int device) {
   return PMP_OK;
 }
 
+// give up a workspace buffer that is being replaced
+int plan_release(pmp_plan* p, void* ptr) {
+  if (p->graphs > 0) {
+    p->retired.push_back(ptr);
+    return PMP_OK;
+  }
+  hipError_t e = hipFree(ptr);
+  if (e != hipSuccess) return hip_fail(e, "hipFree");
+  return PMP_OK;
+}
+
 // make room for n accumulator slots (zeroed)
 int plan_slots(pmp_plan* p, uint64_t n) {
   if (n <= p->nslots) return PMP_OK;
   hipError_t e;
   if (p->slots) {
-    e = hipFree(p->slots);
-    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    int r = plan_release(p, p->slots);
+    if (r) return r;
     p->slots = nullptr;
     p->nslots = 0;
   }
@@ -404,6 +419,7 @@ int pmp_plan_destroy(pmp_plan* plan) {
   if (plan->desc_host) (void)hipHostFree(plan->desc_host);
   if (plan->desc_dev) (void)hipFree(plan->desc_dev);
   if (plan->desc_copied) (void)hipEventDestroy(plan->desc_copied);
+  for (void* q : plan->retired) (void)hipFree(q);
   delete plan;
   return PMP_OK;
 }
@@ -531,6 +547,7 @@ int pmp_graph_create(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, p
   e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return bail(PMP_E_HIP, "hipGraphInstantiate");
   (void)hipStreamDestroy(cs);
+  ++plan->graphs;
   *out = g;
   return PMP_OK;
 }
@@ -548,6 +565,13 @@ int pmp_graph_destroy(pmp_graph* graph) {
   if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
   if (graph->graph) (void)hipGraphDestroy(graph->graph);
   if (graph->desc) (void)hipFree(graph->desc);
+  {
+    std::lock_guard<std::mutex> lk(graph->plan->mu);
+    if (--graph->plan->graphs == 0) {
+      for (void* q : graph->plan->retired) (void)hipFree(q);
+      graph->plan->retired.clear();
+    }
+  }
   delete graph;
   return PMP_OK;
 }
