@@ -161,6 +161,13 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
 __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// A per-lane address in global memory as a pointer the compiler knows to be
+// global: loads through it are global loads (counted by vmcnt alone), not
+// flat ones, whose waits would also drain every outstanding flat load
+// whenever the LDS is read.
+__device__ __forceinline__ const uint8_t* gaddr(uint64_t a) {
+  return (const uint8_t*)(const __attribute__((address_space(1))) uint8_t*)(uintptr_t)a;
+}
 
 template <bool WIDE>
 __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table, int64_t i,
@@ -400,9 +407,10 @@ struct Pieces {
 
 template <bool WIDE, int G>
 __device__ __forceinline__ void block_loads(Pieces<WIDE, G>& P, const uint8_t* blk, int j, uint32_t sh) {
+  const uint8_t* gb = gaddr((uint64_t)(uintptr_t)blk);  // global loads, whatever the pointer's origin
 #pragma unroll
   for (int t = 0; t < Pieces<WIDE, G>::NL; ++t) {
-    const uint8_t* pa = blk + 16 * (t * G + j);
+    const uint8_t* pa = gb + 16 * (t * G + j);
     Q q = load16(pa);
     P.d[t][0] = q.d[0];
     P.d[t][1] = q.d[1];
@@ -467,7 +475,7 @@ __device__ typename Tr<WIDE>::Sum block_guarded(const uint8_t* blk, int j, uint3
     const int P = t * G + j;
     const int64_t rp = r - 16 * (int64_t)P;
     if (rp < 0) continue;  // the piece lies past the padded string
-    const uint8_t* pa = blk + 16 * P;
+    const uint8_t* pa = gaddr((uint64_t)(uintptr_t)(blk + 16 * P));
     const Q q = load16_guarded(pa, lo, hi);
     const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], sh ? load4_guarded(pa + 16, lo, hi) : 0u};
     uint32_t x[4];
@@ -766,7 +774,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       const uint32_t sf = (uint32_t)__shfl((int)f0, src, 64);
       const uint32_t sn = (uint32_t)__shfl((int)nc, src, 64);
       const uint32_t bc = t < nf ? t - sf : sn - 1;  // block of its string
-      blk = v ? (const uint8_t*)(uintptr_t)(sa + (uint64_t)bc * BW) : safe;
+      blk = v ? gaddr(sa + (uint64_t)bc * BW) : safe;
       bsh = v ? ssh : 0u;
       rem = v ? sl - (int64_t)bc * BW : -(int64_t)BW - 64;  // invalid: everything masked
     };
@@ -899,7 +907,7 @@ __device__ __forceinline__ T* gptr(T* p) {
 // batches are read by selection, never by a dynamic index, which would move
 // the whole argument block to scratch.
 __device__ __forceinline__ BatchArgs batch_at(const KArgs& A, uint32_t b) {
-  BatchArgs B = A.batches ? A.batches[b] : (b ? A.b[1] : A.b[0]);
+  BatchArgs B = A.batches ? gptr(A.batches)[b] : (b ? A.b[1] : A.b[0]);
   // a descriptor read from global memory is wave-uniform, but the compiler
   // cannot tell: keep its fields in scalar registers so that addresses built
   // from them (key tables above all) use scalar loads. The pointers are
@@ -951,8 +959,8 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(KArgs A) {
       uint64_t s0 = 0, sw = 0;
       if (b < nb) {
         if (A.batches) {
-          s0 = A.batches[b].work0;
-          sw = A.batches[b].work;
+          s0 = gptr(A.batches)[b].work0;
+          sw = gptr(A.batches)[b].work;
         } else {
           s0 = b ? A.b[1].work0 : A.b[0].work0;
           sw = b ? A.b[1].work : A.b[0].work;
