@@ -72,6 +72,48 @@ def algorithmic_bytes(wl) -> int:
     return tot
 
 
+def algorithmic_mads(wl) -> int:
+    """32x32->64 multiplies of the level-1 sums (Eq. (1), Sec. 6): one per
+    PM+32 word, four per PM+64 word, N' = floor(len / W) + 1 words a string.
+    The upper levels add under 1 % and are not counted."""
+    tot = 0
+    for rg in wl.batches:
+        W = 8 if rg.wide else 4
+        words = int(np.sum(np.diff(rg.offsets) // W + 1))
+        tot += words * (4 if rg.wide else 1)
+    return tot
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# the paper's own single-core numbers (Haswell i7-4770 at 3.4 GHz, long
+# strings), quoted as context only
+PAPER_CONTEXT = {"hardware": "Intel Core i7-4770 (Haswell), one core at 3.4 GHz, AVX2",
+                 "pm32_bytes_per_cycle": 4.7, "pm64_bytes_per_cycle": 3.3,
+                 "pm32_GBps": 16.0, "pm64_GBps": 11.2}
+
+
+def mul_roofline(wl, launch_ms: float) -> dict:
+    """The launch's level-1 multiplies per second against the device's own
+    v_mad_u64_u32 rate (measured now by the library's probe)."""
+    from paper_1609_09840_amd import pmp
+
+    mads = algorithmic_mads(wl)
+    peak = pmp.pmp_probe_mad_rate()
+    achieved = mads / (launch_ms * 1e-3)
+    return {"achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 3), "unit": "T mad32/s",
+            "frac": round(achieved / peak, 4), "mads_per_launch": mads}
+
+
 def setup(wl, dev):
     import torch
 
@@ -137,6 +179,9 @@ def cpu_baseline(wl, target_cpu_s: float = 12.0):
         "unit": "GB/s",
         "cores": threads,
         "kind": "oracle",
+        "single_thread_GBps": round(per_thread / 1e9, 4),
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
         "sample": f"first {nstr} strings ({once} bytes, {100.0 * once / wl.nbytes:.1f}% of the payload, "
                   f"both variants in proportion) hashed {passes} time(s), {tot_s:.2f} s wall on {threads} threads",
     }
@@ -335,6 +380,8 @@ def main():
             "algorithmic_bytes_per_launch": alg,
             "mean_launch_ms": round(launch_ms, 5),
         },
+        "mul_roofline": mul_roofline(wl, launch_ms),
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_plain:
         rec["plain_gpu"] = plain_gpu(keep, dev)

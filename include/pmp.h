@@ -300,6 +300,15 @@ int pmp_hash_plain(int wide, const uint8_t* d_buf, uint64_t buf_bytes, const int
 int pmp_debug_fold(int wide, const void* d_w0, const void* d_w1, const uint32_t* d_w2, void* d_z, int64_t n,
                    pmp_stream_t stream);
 
+/* Measurement hook (not on the path): the rate of v_mad_u64_u32, the
+ * 32x32->64 multiply-add that the level-1 sums of Eq. (1) are built from
+ * (Sec. 6: one per PM+32 word, four per PM+64 word), on the current device,
+ * in lane operations per second: 8 waves per CU's worth of 256-thread blocks
+ * run independent chains. This is the multiply roofline the kernels are
+ * compared with. Allocates and frees a small buffer and a stream;
+ * synchronous (about a millisecond). */
+int pmp_probe_mad_rate(double* mads_per_s);
+
 /* Message for the last error on this thread (never NULL). */
 const char* pmp_last_error(void);
 /* Library version string. */

@@ -54,6 +54,11 @@ namespace pmp {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace pmp
 
+namespace pmp {
+// the multiply-rate probe (pmp_probe.hip): `blocks` blocks of 256 threads
+hipError_t launch_mad_probe(uint64_t* out, int blocks, uint32_t iters, hipStream_t s);
+}  // namespace pmp
+
 struct pmp_plan {
   int device = 0;
   int32_t* status = nullptr;  // device
@@ -665,6 +670,41 @@ int pmp_debug_fold(int wide, const void* d_w0, const void* d_w1, const uint32_t*
   if (n == 0) return PMP_OK;
   hipError_t e = pmp::launch_debug_fold(wide, d_w0, d_w1, d_w2, d_z, n, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "fold launch");
+  return PMP_OK;
+}
+
+int pmp_probe_mad_rate(double* mads_per_s) {
+  if (!mads_per_s) return fail(PMP_E_INVALID_ARG, "mads_per_s is NULL");
+  *mads_per_s = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "device properties");
+  const int blocks = prop.multiProcessorCount * 8;  // 8 waves per SIMD's worth of lanes
+  const uint32_t iters = 4096;
+  uint64_t* out = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipMalloc(&out, (size_t)blocks * 256 * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(PMP_E_NOMEM, "probe buffer: %s", hipGetErrorString(e));
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float ms = 0;
+  if (e == hipSuccess) e = pmp::launch_mad_probe(out, blocks, iters, s);  // warm
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = pmp::launch_mad_probe(out, blocks, iters, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(out);
+  if (e != hipSuccess) return hip_fail(e, "mad probe");
+  if (ms <= 0) return fail(PMP_E_HIP, "mad probe took no time");
+  *mads_per_s = 3.0 * blocks * 256.0 * iters * 8.0 / (ms * 1e-3);
   return PMP_OK;
 }
 

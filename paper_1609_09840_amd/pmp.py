@@ -121,6 +121,7 @@ def _load():
         "pmp_plan_status": [vp, vp],
         "pmp_plan_set_tile": [vp, i32, i32],
         "pmp_plan_tune": [vp, i32, u32, u64, i32],
+        "pmp_probe_mad_rate": [ctypes.POINTER(ctypes.c_double)],
         "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
@@ -447,6 +448,14 @@ def pmp_hash_plain(wide: bool, buf, h_offsets: np.ndarray, keys, out, flags: int
                                _dev_ptr(scratch, "scratch"), scratch.numel() * scratch.element_size(),
                                _stream(stream)))
     return out
+
+
+def pmp_probe_mad_rate() -> float:
+    """v_mad_u64_u32 lane operations per second on the current device (the
+    multiply roofline)."""
+    r = ctypes.c_double(0.0)
+    _check(_lib.pmp_probe_mad_rate(ctypes.byref(r)))
+    return r.value
 
 
 def pmp_debug_fold(wide: bool, w0, w1, w2, z, stream=None):

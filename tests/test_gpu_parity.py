@@ -316,3 +316,13 @@ def test_stage_overflow_passes(wide, lead):
         assert U.first_mismatch(got, want) is None, (name, U.first_mismatch(got, want))
     assert plan.status() == pmp.PMP_OK
     plan.close()
+
+
+def test_mad_probe_rate():
+    """The multiply-rate probe returns a plausible rate (between 1 T and
+    1000 T lane operations per second on one device)."""
+    from paper_1609_09840_amd import pmp
+
+    say("case mad probe")
+    r = pmp.pmp_probe_mad_rate()
+    assert 1e12 < r < 1e15, r
