@@ -130,6 +130,7 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // longer strings, or strings cut by the share's ends, by the whole wave.
 constexpr uint32_t TINY_GROUPS = 16;
 constexpr int64_t MEDIUM_BLOCKS = 32;
+static_assert(MEDIUM_BLOCKS + 4 <= BLOCK, "level-2 reads of medium strings run up to 3 keys past the last block");
 
 // ---------------------------------------------------------------------------
 // Strings of at most TINY_GROUPS groups, one per lane, read from LDS.
@@ -820,12 +821,21 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     Sum acc2;
     zero(acc2);
     Fe res = {0, 0};
-    for (uint32_t c = 0; c < mc; ++c) {
-      const bool on = in && c < nc;
-      const uint32_t tk = c + 1 < nc ? f0 + c : tlast;
-      const Fe z = {on ? zl[2 * tk] : 0ull, on ? (uint32_t)zl[2 * tk + 1] : 0u};
-      if (c == 0) res = z;
-      mac_fe(acc2, (typename T::key_t)lk[BLOCK + c], z);
+    // four elements per round trip: their LDS reads are issued together
+    for (uint32_t cb = 0; cb < mc; cb += 4) {
+      Fe zz[4];
+      typename T::key_t kk[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t c = cb + (uint32_t)q;  // < mc + 3 <= MEDIUM_BLOCKS + 3: inside the level-2 keys
+        const bool on = in && c < nc;
+        const uint32_t tk = c + 1 < nc ? f0 + c : tlast;
+        zz[q] = Fe{on ? zl[2 * tk] : 0ull, on ? (uint32_t)zl[2 * tk + 1] : 0u};
+        kk[q] = (typename T::key_t)lk[BLOCK + c];
+      }
+      if (cb == 0) res = zz[0];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mac_fe(acc2, kk[q], zz[q]);  // a zero element adds nothing
     }
     if (in) {
       if (nc > 1) {
