@@ -404,10 +404,19 @@ template <bool WIDE, int G>
 struct Pieces {
   static constexpr int NL = BLOCK * Tr<WIDE>::W / 16 / G;  // pieces per lane
   uint32_t d[NL][5];
+  uint32_t b[2];  // the dword pair that holds the string's end, when the block has it
 };
 
+// Byte offset, from a block's 4-aligned start, of the dword pair that holds
+// the first byte past the string (rem = string bytes from the block's start;
+// 0 when the string goes on past the block)
+__device__ __forceinline__ uint32_t end_dword(int64_t rem, int64_t bw) {
+  return rem >= 0 && rem < bw ? (uint32_t)rem & ~3u : 0u;
+}
+
 template <bool WIDE, int G>
-__device__ __forceinline__ void block_loads(Pieces<WIDE, G>& P, const uint8_t* blk, int j, uint32_t sh) {
+__device__ __forceinline__ void block_loads(Pieces<WIDE, G>& P, const uint8_t* blk, int j, uint32_t sh,
+                                            uint32_t eoff) {
   const uint8_t* gb = gaddr((uint64_t)(uintptr_t)blk);  // global loads, whatever the pointer's origin
 #pragma unroll
   for (int t = 0; t < Pieces<WIDE, G>::NL; ++t) {
@@ -421,8 +430,16 @@ __device__ __forceinline__ void block_loads(Pieces<WIDE, G>& P, const uint8_t* b
     // condition would make the compiler drain every load before its use)
     P.d[t][4] = *(const uint32_t*)__builtin_assume_aligned(pa + 16, 4);
   }
+  // (eoff < 128 W, so these 8 bytes lie within the block's 128 W + 4)
+  P.b[0] = *(const uint32_t*)__builtin_assume_aligned(gb + eoff, 4);
+  P.b[1] = *(const uint32_t*)__builtin_assume_aligned(gb + eoff + 4, 4);
 }
 
+// A TAIL block may hold the string's end: a dword is summed only when all of
+// its bytes are string bytes, and the dword that holds the first byte past
+// the string (its own last bytes, the pad byte 0x01 and zeros: Sec. 4) is
+// added once, by the lane whose piece holds it, from the pair P.b that
+// block_loads read for it. Dwords past it are zero (padded string) and dropped.
 template <bool WIDE, int G, bool TAIL>
 __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G>& P, int j, uint32_t sh,
                                                             const uint64_t* lk, bool act, int64_t rem) {
@@ -430,19 +447,21 @@ __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G
   constexpr int W = T::W;
   constexpr int WPP = 16 / W;  // words per piece
   constexpr int NL = Pieces<WIDE, G>::NL;
-  const int64_t r = act ? rem : -(int64_t)(BLOCK * W) - 64;  // inactive: everything masked
+  constexpr int32_t BW = BLOCK * W;
   typename T::Sum acc;
   P64 p;
   zero(acc);
   zero(p);
+  // string bytes from the block's start, clamped (inactive: every dword dropped)
+  const int32_t rr = !TAIL ? BW : !act ? -16 : rem < -16 ? -16 : rem > BW ? BW : (int32_t)rem;
+  const int32_t rj = rr - 16 * j - 4;  // dword u of piece t is kept when 16 G t + 4 u <= rj
 #pragma unroll
   for (int t = 0; t < NL; ++t) {
     uint32_t x[4];
-    if constexpr (TAIL) {
-      group_words<WIDE>(P.d[t], sh, r - 16 * (int64_t)(t * G + j), x);
-    } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = align_bytes(P.d[t][u + 1], P.d[t][u], sh);
+    for (int u = 0; u < 4; ++u) {
+      x[u] = align_bytes(P.d[t][u + 1], P.d[t][u], sh);
+      if constexpr (TAIL) x[u] = 16 * G * t + 4 * u <= rj ? x[u] : 0u;
     }
     const uint64_t* kp = lk + WPP * (t * G + j);
     if constexpr (WIDE) {
@@ -451,6 +470,20 @@ __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u) mac_vv(acc.lo, acc.hi, (uint32_t)kp[u], x[u]);
+    }
+  }
+  if constexpr (TAIL) {
+    if (rr >= 0 && rr < BW && ((rr >> 4) % G) == j) {
+      const uint32_t qb = (uint32_t)rr & 3u;  // string bytes in the end dword
+      const uint32_t xb = align_bytes(P.b[1], P.b[0], sh);
+      const uint32_t v = (xb & ((1u << (8 * qb)) - 1u)) | (1u << (8 * qb));
+      const int32_t bd = rr >> 2;  // its dword in the block
+      if constexpr (WIDE) {
+        const bool high = bd & 1;
+        mac64_vv(p, lk[bd >> 1], high ? 0u : v, high ? v : 0u);
+      } else {
+        mac_vv(acc.lo, acc.hi, (uint32_t)lk[bd], v);
+      }
     }
   }
   if constexpr (WIDE) acc = collapse(p);
@@ -528,14 +561,16 @@ __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint64_t
   zero(acc2);
   Pieces<WIDE, G> nxt;
   bool have = plain(bl);
-  block_loads<WIDE, G>(nxt, have ? a4 + (bl + g) * (int64_t)(BLOCK * W) : safe, j, sh);
+  block_loads<WIDE, G>(nxt, have ? a4 + (bl + g) * (int64_t)(BLOCK * W) : safe, j, sh,
+                       end_dword(len - (bl + g) * (int64_t)(BLOCK * W), BLOCK * W));
   for (int64_t c0 = bl; c0 < bh; c0 += CPS) {
     // keys stay in LDS: reading them again each step keeps registers free
     asm volatile("" ::: "memory");
     const Pieces<WIDE, G> cur = nxt;
     const bool cur_loaded = have;
     have = plain(c0 + CPS);
-    block_loads<WIDE, G>(nxt, have ? a4 + (c0 + CPS + g) * (int64_t)(BLOCK * W) : safe, j, sh);
+    block_loads<WIDE, G>(nxt, have ? a4 + (c0 + CPS + g) * (int64_t)(BLOCK * W) : safe, j, sh,
+                         end_dword(len - (c0 + CPS + g) * (int64_t)(BLOCK * W), BLOCK * W));
     const int64_t c = c0 + g;
     const bool act = c < bh;
     const uint8_t* blk = a4 + c * (int64_t)(BLOCK * W);
@@ -730,7 +765,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       bs = block_guarded<WIDE, G>(blk, j, ssh, lk, act, sl, lo, hi);
     } else {
       Pieces<WIDE, G> P;
-      block_loads<WIDE, G>(P, blk, j, ssh);
+      block_loads<WIDE, G>(P, blk, j, ssh, end_dword(act ? sl : -1, BW));
       bs = block_sum<WIDE, G, true>(P, j, ssh, lk, act, sl);
     }
     group_sum<G>(bs);
@@ -786,7 +821,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     task((uint32_t)g, nblk, nsh, nrem);
     bool have = (uint32_t)g < tr && inside(nblk, BW + 4, lo, hi);
     Pieces<WIDE, G> nxt;
-    block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh);
+    block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh, end_dword(nrem, BW));
     for (uint32_t st = 0; st < steps; ++st) {
       asm volatile("" ::: "memory");  // keys stay in LDS
       const Pieces<WIDE, G> cur = nxt;
@@ -800,7 +835,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       // the group's next task, loaded while this one is summed
       task(t + CPS, nblk, nsh, nrem);
       have = t + CPS < tr && inside(nblk, BW + 4, lo, hi);
-      block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh);
+      block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh, end_dword(nrem, BW));
       Sum bs;
       if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, bsh, lk, act, rem, lo, hi);
       else if (full) bs = block_sum<WIDE, G, false>(cur, j, bsh, lk, true, 0);
