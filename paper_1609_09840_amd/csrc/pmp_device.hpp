@@ -82,12 +82,20 @@ __device__ __forceinline__ void add_word(S64& s, uint64_t b) {
 }
 
 // PM+64 word x = (x0, x1), key a = (a0, a1): add a * x to the partial sums.
+// The four multiply-adds go first and their carry adds after, each carry in
+// its own register pair, so that no carry is read right after it is written
+// (which would cost wait states).
 __device__ __forceinline__ void mac64_vv(P64& s, uint64_t a, uint32_t x0, uint32_t x1) {
   uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  mac_vv(s.p0, s.c0, a0, x0);
-  mac_vv(s.p1, s.c1, a0, x1);
-  mac_vv(s.p1, s.c1, a1, x0);
-  mac_vv(s.p2, s.c2, a1, x1);
+  uint64_t k0, k1, k2, k3;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.p0), "=s"(k0) : "v"(a0), "v"(x0));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.p1), "=s"(k1) : "v"(a0), "v"(x1));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.p2), "=s"(k2) : "v"(a1), "v"(x1));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.p1), "=s"(k3) : "v"(a1), "v"(x0));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.c0), "+s"(k0));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.c1), "+s"(k1));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.c2), "+s"(k2));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.c1), "+s"(k3));
 }
 __device__ __forceinline__ void mac64_sv(P64& s, uint64_t a, uint32_t x0, uint32_t x1) {
   uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
