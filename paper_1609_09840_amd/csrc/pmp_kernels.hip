@@ -559,18 +559,11 @@ __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint64_t
 
   Sum acc2;
   zero(acc2);
-  Pieces<WIDE, G> nxt;
-  bool have = plain(bl);
-  block_loads<WIDE, G>(nxt, have ? a4 + (bl + g) * (int64_t)(BLOCK * W) : safe, j, sh,
-                       end_dword(len - (bl + g) * (int64_t)(BLOCK * W), BLOCK * W));
-  for (int64_t c0 = bl; c0 < bh; c0 += CPS) {
+  // one step: blocks c0 .. c0 + CPS - 1, held in `cur` (read plainly) or
+  // read piece by piece at the buffer's edges
+  auto step = [&](const Pieces<WIDE, G>& cur, bool cur_loaded, int64_t c0) {
     // keys stay in LDS: reading them again each step keeps registers free
     asm volatile("" ::: "memory");
-    const Pieces<WIDE, G> cur = nxt;
-    const bool cur_loaded = have;
-    have = plain(c0 + CPS);
-    block_loads<WIDE, G>(nxt, have ? a4 + (c0 + CPS + g) * (int64_t)(BLOCK * W) : safe, j, sh,
-                         end_dword(len - (c0 + CPS + g) * (int64_t)(BLOCK * W), BLOCK * W));
     const int64_t c = c0 + g;
     const bool act = c < bh;
     const uint8_t* blk = a4 + c * (int64_t)(BLOCK * W);
@@ -584,6 +577,25 @@ __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint64_t
     add_word(blk_sum, b1);
     const Fe z = reduce(blk_sum);
     if (act) mac_fe(acc2, (typename T::key_t)lk[BLOCK + (c - nb)], z);
+  };
+  // the loads of step c0 (and where they came from)
+  auto fill = [&](Pieces<WIDE, G>& P, bool& h, int64_t c0) {
+    h = plain(c0);
+    block_loads<WIDE, G>(P, h ? a4 + (c0 + g) * (int64_t)(BLOCK * W) : safe, j, sh,
+                         end_dword(len - (c0 + g) * (int64_t)(BLOCK * W), BLOCK * W));
+  };
+  // two buffers used in turn, the loop unrolled twice so that neither is
+  // ever copied (a copy costs a move per register and waits for the loads):
+  // the next step's loads are issued before this one is summed
+  Pieces<WIDE, G> pa, pb;
+  bool ha, hb;
+  fill(pa, ha, bl);
+  for (int64_t c0 = bl; c0 < bh; c0 += 2 * CPS) {
+    fill(pb, hb, c0 + CPS);
+    step(pa, ha, c0);
+    if (c0 + CPS >= bh) break;
+    fill(pa, ha, c0 + 2 * CPS);
+    step(pb, hb, c0 + CPS);
   }
   reduce_lanes(acc2, G, 64);
   return acc2;
@@ -815,31 +827,28 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       rem = v ? sl - (int64_t)bc * BW : -(int64_t)BW - 64;  // invalid: everything masked
     };
     const uint32_t steps = (tr + CPS - 1) / CPS;
-    const uint8_t* nblk;
-    uint32_t nsh;
-    int64_t nrem;
-    task((uint32_t)g, nblk, nsh, nrem);
-    bool have = (uint32_t)g < tr && inside(nblk, BW + 4, lo, hi);
-    Pieces<WIDE, G> nxt;
-    block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh, end_dword(nrem, BW));
-    for (uint32_t st = 0; st < steps; ++st) {
+    // a task's block, where it was read from, and its loads
+    struct Tk {
+      const uint8_t* blk;
+      uint32_t sh;
+      int64_t rem;
+      bool have;  // read with plain loads
+    };
+    auto issue = [&](Pieces<WIDE, G>& P, uint32_t t, Tk& k) {
+      task(t, k.blk, k.sh, k.rem);
+      k.have = t < tr && inside(k.blk, BW + 4, lo, hi);
+      block_loads<WIDE, G>(P, k.have ? k.blk : safe, j, k.sh, end_dword(k.rem, BW));
+    };
+    // the group's task of step st: sum, fold, field element to LDS
+    auto compute = [&](const Pieces<WIDE, G>& P, const Tk& k, uint32_t st) {
       asm volatile("" ::: "memory");  // keys stay in LDS
-      const Pieces<WIDE, G> cur = nxt;
-      const bool cur_loaded = have;
       const uint32_t t = st * CPS + (uint32_t)g;
       const bool act = t < tr;
       const bool full = (st + 1) * CPS <= nf;  // uniform: every block of this step is full
-      const uint8_t* blk = nblk;
-      const uint32_t bsh = nsh;
-      const int64_t rem = nrem;
-      // the group's next task, loaded while this one is summed
-      task(t + CPS, nblk, nsh, nrem);
-      have = t + CPS < tr && inside(nblk, BW + 4, lo, hi);
-      block_loads<WIDE, G>(nxt, have ? nblk : safe, j, nsh, end_dword(nrem, BW));
       Sum bs;
-      if (__ballot(act && !cur_loaded)) bs = block_guarded<WIDE, G>(blk, j, bsh, lk, act, rem, lo, hi);
-      else if (full) bs = block_sum<WIDE, G, false>(cur, j, bsh, lk, true, 0);
-      else bs = block_sum<WIDE, G, true>(cur, j, bsh, lk, act, rem);
+      if (__ballot(act && !k.have)) bs = block_guarded<WIDE, G>(k.blk, j, k.sh, lk, act, k.rem, lo, hi);
+      else if (full) bs = block_sum<WIDE, G, false>(P, j, k.sh, lk, true, 0);
+      else bs = block_sum<WIDE, G, true>(P, j, k.sh, lk, act, k.rem);
       group_sum<G>(bs);
       add_word(bs, b1);
       const Fe z = reduce(bs);
@@ -847,6 +856,18 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
         zl[2 * t] = z.lo;
         zl[2 * t + 1] = z.hi;
       }
+    };
+    // two buffers used in turn (unrolled twice: neither is ever copied); the
+    // next step's blocks are loaded while this one is summed
+    Pieces<WIDE, G> pa, pb;
+    Tk ka, kb;
+    issue(pa, (uint32_t)g, ka);
+    for (uint32_t st = 0; st < steps; st += 2) {
+      issue(pb, (st + 1) * CPS + (uint32_t)g, kb);
+      compute(pa, ka, st);
+      if (st + 1 >= steps) break;
+      issue(pa, (st + 2) * CPS + (uint32_t)g, ka);
+      compute(pb, kb, st + 1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
