@@ -145,8 +145,9 @@ static_assert(MEDIUM_BLOCKS + 4 <= BLOCK, "level-2 reads of medium strings run u
 // consecutive slots mostly belong to one string the loads are coalesced.
 // Lanes that do not fit go in a further pass. Each lane then writes the pad
 // (Sec. 4: a byte 0x01, zeros to the end of its slots) into its own copy, so
-// that the words of its padded string read straight out of the stage; words
-// past the padded end are dropped by one compare each. The group's keys are
+// that the words of its padded string read straight out of the stage; its
+// slots cover every group it reads, so the words past the padded end read as
+// zero, and a lane sits out the groups past its string's end. The group's keys are
 // wave-uniform LDS reads (broadcast) and the products are summed exactly with
 // v_mad_u64_u32 plus a carry counter (one fold per string).
 constexpr uint32_t STAGE_CHUNKS = 768;             // 12 KiB of string bytes per wave
@@ -187,7 +188,12 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
   // chunks [a16, a16 + 16 nl) hold the string (none for an empty one: its
   // buffer may be empty); ns slots leave room for the pad word
   const uint32_t nl = act && ulen > 0 ? (lead + ulen + 15) / 16 : 0u;
-  const uint32_t ns = act ? (lead + ulen + W + 15) / 16 : 0u;
+  // (and every group the lane reads, 4 bytes past the last one included:
+  // the stage is zero from the pad to the end of the slots, so the words past
+  // the padded string read as zero and need no mask)
+  const uint32_t ns0 = act ? (lead + ulen + W + 15) / 16 : 0u;
+  const uint32_t ns1 = act ? ((lead & ~3u) + 16 * ((pbytes + 15) / 16) + 4 + 15) / 16 : 0u;
+  const uint32_t ns = ns0 > ns1 ? ns0 : ns1;
   uint64_t total = 0;
   const uint32_t c0 = (uint32_t)wave_excl_scan(ns, &total);
   const typename T::key_t* __restrict__ keys = (const typename T::key_t*)B.keys;
@@ -247,13 +253,14 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
     }
     const uint32_t maxg = wave_max(in ? (pbytes + 15) / 16 : 0u);
     const uint32_t p0 = in ? r0 + (lead & ~3u) : 0u;
-    const uint32_t pe = in ? pbytes : 0u;  // words at or past pe are not part of the padded string
     typename T::Sum acc;
     zero(acc);
     P64 p;
     zero(p);
     constexpr int KPG = WIDE ? 2 : 4;  // keys per group
+    const uint32_t ng = in ? (pbytes + 15) / 16 : 0u;  // this lane's groups
     for (uint32_t g = 0; g < maxg; ++g) {
+      if (g >= ng) continue;  // lanes past their string's end sit out
       const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
       uint32_t d[5];
       uint64_t kk[KPG];
@@ -265,10 +272,7 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
       __builtin_amdgcn_sched_barrier(0);
       uint32_t x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint32_t v = align_bytes(d[u + 1], d[u], sh);
-        x[u] = 16 * g + 4 * u < pe ? v : 0u;
-      }
+      for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
       if constexpr (WIDE) {
         mac64_sv(p, kk[0], x[0], x[1]);
         mac64_sv(p, kk[1], x[2], x[3]);
