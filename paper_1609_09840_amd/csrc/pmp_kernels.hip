@@ -214,7 +214,14 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
     // the previous tile's output stores before each entry)
     if (in) {
       const uint32_t ta = lds_addr(table) + 4 * (c0 - base);
-      for (uint32_t t = 0; t < ns; ++t) {
+      // two entries per write
+      for (uint32_t t = 0; t + 1 < ns; t += 2) {
+        const uint32_t v0 = t < nl ? (uint32_t)rel + t : NO_CHUNK;
+        const uint32_t v1 = t + 1 < nl ? (uint32_t)rel + t + 1 : NO_CHUNK;
+        asm volatile("ds_write2_b32 %0, %1, %2 offset1:1" ::"v"(ta + 4 * t), "v"(v0), "v"(v1) : "memory");
+      }
+      if (ns & 1u) {
+        const uint32_t t = ns - 1;
         const uint32_t v = t < nl ? (uint32_t)rel + t : NO_CHUNK;
         asm volatile("ds_write_b32 %0, %1" ::"v"(ta + 4 * t), "v"(v) : "memory");
       }
