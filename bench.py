@@ -214,12 +214,15 @@ def plain_gpu(keep, dev, max_strings: int = 4000):
             "sample": f"first {nstr} strings of the batch ({tot_bytes} bytes), same outputs as the batched path"}
 
 
-def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505):
+def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505, per_launch: int = 16,
+                  sat_passes: int = 8):
     """Serving workload: Poisson arrivals of requests of 1..4096 strings with
     lengths log-uniform in [16 B, 64 KiB], variant per request, payloads
     pre-staged in a device-resident pool (the device batching is measured, not
-    PCIe). The saturation rate is measured first (the whole pool submitted at
-    once); then `points` rates from 0.1x to 1.2x of it, geometric."""
+    PCIe). The saturation rate is measured first (the pool submitted
+    `sat_passes` times over, all at once, at most `per_launch` requests per
+    launch so that the lanes overlap); then `points` rates from 0.1x to 1.2x
+    of it, geometric."""
     import torch
 
     from paper_1609_09840_amd import pmp
@@ -237,12 +240,12 @@ def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505):
     mean_bytes = float(np.mean([p[0].nbytes for p in pool]))
     k32 = torch.from_numpy(pmp.pmp_expand_keys32(W.KEY_SEED32).view(np.int32)).to(dev).view(torch.uint32)
     k64 = torch.from_numpy(pmp.pmp_expand_keys64(W.KEY_SEED64).view(np.int64)).to(dev).view(torch.uint64)
-    srv = pmp.Server(k32, k64, device=0, lanes=4, lane_bytes=0, max_requests_per_batch=64,
+    srv = pmp.Server(k32, k64, device=0, lanes=4, lane_bytes=0, max_requests_per_batch=per_launch,
                      reserve_bytes=64 << 20)
     try:
         srv.replay(reqs, np.zeros(len(reqs)))  # warm-up
         srv.reset_stats()
-        srv.replay(reqs * 2, np.zeros(2 * len(reqs)))
+        srv.replay(reqs * sat_passes, np.zeros(sat_passes * len(reqs)))
         st = srv.stats()
         sat_rps = st["completed"] / (st["span_us"] * 1e-6)
         rows = []
@@ -264,6 +267,7 @@ def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505):
         srv.close()
     return {"mean_request_bytes": round(mean_bytes), "saturation_rps": round(float(sat_rps), 2),
             "saturation_GBps": round(sat_rps * mean_bytes / 1e9, 2), "lanes": 4,
+            "max_requests_per_launch": per_launch,
             "payload": "device-resident pool of %d requests" % pool_size, "sweep": rows}
 
 
