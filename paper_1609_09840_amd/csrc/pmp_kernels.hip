@@ -130,7 +130,7 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // longer strings, or strings cut by the share's ends, by the whole wave.
 constexpr uint32_t TINY_GROUPS = 16;
 constexpr int64_t MEDIUM_BLOCKS = 32;
-static_assert(MEDIUM_BLOCKS + 4 <= BLOCK, "level-2 reads of medium strings run up to 3 keys past the last block");
+static_assert(MEDIUM_BLOCKS <= BLOCK, "a medium string is one level-2 node");
 
 // ---------------------------------------------------------------------------
 // Strings of at most TINY_GROUPS groups, one per lane, read from LDS.
@@ -746,6 +746,7 @@ __device__ void locate2(const BatchArgs& B, uint32_t alpha, uint64_t x0, uint64_
 // take a further round. `med` marks lanes whose string (i, o0, len, C1) is
 // medium; `zbuf` and `tab` are the wave's stage and table.
 constexpr uint32_t MEDIUM_TASKS = STAGE_BYTES / 16;  // field elements held at once
+static_assert(64 * 4 * 8 <= 4 * STAGE_CHUNKS, "the level-2 limb sums of 64 strings fit the task table");
 
 template <bool WIDE, int G>
 __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* zbuf, uint32_t* tab, bool med,
@@ -824,7 +825,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the block of task t, for this lane's group (every lane takes part in
     // the shuffles: ds_bpermute reads 0 from a disabled source lane)
-    auto task = [&](uint32_t t, const uint8_t*& blk, uint32_t& bsh, int64_t& rem) {
+    auto task = [&](uint32_t t, const uint8_t*& blk, uint32_t& bsh, int64_t& rem, uint32_t& own) {
       const bool v = t < tr;
       const int src = v ? (int)tab[t] : lane;
       const uint64_t sa = (uint64_t)__shfl((long long)(uint64_t)(uintptr_t)a4, src, 64);
@@ -836,6 +837,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       blk = v ? gaddr(sa + (uint64_t)bc * BW) : safe;
       bsh = v ? ssh : 0u;
       rem = v ? sl - (int64_t)bc * BW : -(int64_t)BW - 64;  // invalid: everything masked
+      own = (uint32_t)src | (bc << 8);                       // its string's lane and block
     };
     const uint32_t steps = (tr + CPS - 1) / CPS;
     // a task's block, where it was read from, and its loads
@@ -843,10 +845,11 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       const uint8_t* blk;
       uint32_t sh;
       int64_t rem;
-      bool have;  // read with plain loads
+      uint32_t own;  // lane of its string | block << 8
+      bool have;     // read with plain loads
     };
     auto issue = [&](Pieces<WIDE, G>& P, uint32_t t, Tk& k) {
-      task(t, k.blk, k.sh, k.rem);
+      task(t, k.blk, k.sh, k.rem, k.own);
       k.have = t < tr && inside(k.blk, BW + 4, lo, hi);
       block_loads<WIDE, G>(P, k.have ? k.blk : safe, j, k.sh, end_dword(k.rem, BW));
     };
@@ -865,7 +868,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       const Fe z = reduce(bs);
       if (act && j == 0) {
         zl[2 * t] = z.lo;
-        zl[2 * t + 1] = z.hi;
+        zl[2 * t + 1] = z.hi | ((uint64_t)k.own << 32);
       }
     };
     // two buffers used in turn (unrolled twice: neither is ever copied); the
@@ -883,31 +886,64 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // level 2, one lane per string
-    const uint32_t mc = wave_max(in ? nc : 0u);
-    Sum acc2;
-    zero(acc2);
-    Fe res = {0, 0};
-    // four elements per round trip: their LDS reads are issued together
-    for (uint32_t cb = 0; cb < mc; cb += 4) {
-      Fe zz[4];
-      typename T::key_t kk[4];
+    // Level 2: b_2 + sum_c a_{2,c} z_c per string. The lanes share the
+    // tasks (lane l takes tasks l, l + 64, ...) and add a_{2,c} z_c into the
+    // string's sums in LDS (the task table is free now) as 32-bit limbs,
+    // each summed in 64 bits (at most 32 terms of < 2^33: no overflow); then
+    // the string's lane joins the limbs exactly and folds the total.
+    constexpr int NLIMB = WIDE ? 4 : 2;
+    using L2 = __attribute__((address_space(3))) uint64_t;
+    L2* l2 = (L2*)(uintptr_t)lds_addr(tab);  // 64 strings x NLIMB sums
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t c = cb + (uint32_t)q;  // < mc + 3 <= MEDIUM_BLOCKS + 3: inside the level-2 keys
-        const bool on = in && c < nc;
-        const uint32_t tk = c + 1 < nc ? f0 + c : tlast;
-        zz[q] = Fe{on ? zl[2 * tk] : 0ull, on ? (uint32_t)zl[2 * tk + 1] : 0u};
-        kk[q] = (typename T::key_t)lk[BLOCK + c];
+    for (int q = 0; q < NLIMB; ++q) l2[NLIMB * lane + q] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t t = (uint32_t)lane; t < tr; t += 64) {
+      const uint64_t zlo = zl[2 * t];
+      const uint64_t zhw = zl[2 * t + 1];
+      const uint32_t own = (uint32_t)(zhw >> 32);
+      const bool zh = zhw & 1u;
+      const uint32_t sl = own & 63u;
+      const uint64_t a = (uint64_t)(typename T::key_t)lk[BLOCK + (own >> 8)];
+      uint64_t limb[NLIMB];
+      if constexpr (WIDE) {
+        const u128 pr = (u128)a * zlo;  // a z = a zlo + 2^64 a zh
+        limb[0] = (uint32_t)pr;
+        limb[1] = (uint32_t)(pr >> 32);
+        limb[2] = (uint64_t)(uint32_t)(pr >> 64) + (zh ? (uint32_t)a : 0u);
+        limb[3] = (uint64_t)(uint32_t)(pr >> 96) + (zh ? (uint32_t)(a >> 32) : 0u);
+      } else {
+        const uint64_t pr = a * zlo;  // a z = a zlo + 2^32 a zh
+        limb[0] = (uint32_t)pr;
+        limb[1] = (pr >> 32) + (zh ? a : 0u);
       }
-      if (cb == 0) res = zz[0];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) mac_fe(acc2, kk[q], zz[q]);  // a zero element adds nothing
+      for (int q = 0; q < NLIMB; ++q)
+        __hip_atomic_fetch_add(&l2[NLIMB * sl + q], limb[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (in) {
+      Fe res;
       if (nc > 1) {
+        Sum acc2;
+        if constexpr (WIDE) {
+          const u128 lo = (u128)l2[NLIMB * lane] + ((u128)l2[NLIMB * lane + 1] << 32);
+          const u128 hi = (u128)l2[NLIMB * lane + 2] + ((u128)l2[NLIMB * lane + 3] << 32) + (uint64_t)(lo >> 64);
+          acc2.w0 = (uint64_t)lo;
+          acc2.w1 = (uint64_t)hi;
+          acc2.w2 = (uint32_t)(hi >> 64);
+        } else {
+          const u128 v = (u128)l2[NLIMB * lane] + ((u128)l2[NLIMB * lane + 1] << 32);
+          acc2.lo = (uint64_t)v;
+          acc2.hi = (uint32_t)(v >> 64);
+        }
         add_word(acc2, b2);
         res = reduce(acc2);
+      } else {  // one block: its element is the hash
+        res = Fe{zl[2 * tlast], (uint32_t)(zl[2 * tlast + 1] & 1u)};
       }
       store_out<WIDE>(B, i, res);
     }
@@ -1013,7 +1049,7 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(KArgs A) {
   // the direct-to-LDS loads write only `stages`: the compiler then waits for
   // them before reads of `stages` alone, not before those of the tables
   __shared__ __attribute__((aligned(16))) uint8_t stages[4][STAGE_BYTES + STAGE_SLACK];
-  __shared__ uint32_t tables[4][STAGE_CHUNKS];
+  __shared__ __attribute__((aligned(16))) uint32_t tables[4][STAGE_CHUNKS];
   const int lane = lane_id();
   uint64_t* lk = lkeys[threadIdx.x / 64];
   uint8_t* stage = stages[threadIdx.x / 64];
