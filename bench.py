@@ -321,7 +321,7 @@ def main():
             plan.set_tile(True, args.g64)
         plan.tune(args.waves_per_cu, args.alpha, 0, args.shares)
         tuning = {"source": "command line", "g32": plan_g(args.g32), "g64": plan_g(args.g64, True),
-                  "alpha": args.alpha or 1024, "waves_per_cu": args.waves_per_cu, "shares_per_wave": args.shares or 1}
+                  "alpha": args.alpha or 768, "waves_per_cu": args.waves_per_cu, "shares_per_wave": args.shares or 1}
     else:  # the library's autotuner, on this workload, before the warm-up
         tuning = pmp.pmp_plan_autotune(plan, [b for b in batches if b is not None], stream=stream)
         tuning = {"source": "pmp_plan_autotune", **{k: (round(v, 4) if isinstance(v, float) else v)
@@ -397,7 +397,7 @@ def main():
 
 
 def plan_g(g: int, wide: bool = False) -> int:
-    return g if g else (16 if wide else 8)
+    return g if g else 8  # the plan default: 8 lanes per block for both variants
 
 
 if __name__ == "__main__":

@@ -105,13 +105,13 @@ int pmp_plan_reserve(pmp_plan* plan, uint64_t max_buf_bytes, int64_t max_count);
  * the workspace so that the plan can be used again. */
 int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream);
 /* Lanes per 128-word block for strings longer than one block, per variant
- * (wide = 0: PM+32, 1: PM+64; 0 = the default, 8 and 16). Compiled pairs:
+ * (wide = 0: PM+32, 1: PM+64; 0 = the default, 8 and 8). Compiled pairs:
  * (8,16) (8,8) (16,16) (4,16) (16,8) (4,8); others give PMP_E_INVALID_ARG.
  * Set by the autotuner or by hand. */
 int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block);
 /* Launch shape: waves per CU (0 = as many as stay resident), the per-string
  * work weight alpha in byte equivalents used to split a batch between waves
- * (0 = keep; a new plan has 1024), the smallest share of work worth a wave
+ * (0 = keep; a new plan has 768), the smallest share of work worth a wave
  * (0 = keep; a new plan has 8192), and the
  * number of shares each wave takes, spread over the batch (1..64, 0 = keep;
  * more shares even out regions of the batch that cost more per byte, at a
@@ -190,7 +190,8 @@ int pmp_graph_launch(pmp_graph* graph, pmp_stream_t stream);
 int pmp_graph_destroy(pmp_graph* graph);
 
 /* Autotuner: times pmp_hash_many(plan, batches, nbatch, stream) over every
- * compiled lanes-per-block pair and per-string weight alpha in {128, 512, 1024, 2048},
+ * compiled lanes-per-block pair and per-string weight alpha in {256, 512, 768, 1024,
+ * 1536, 2048},
  * then over 1, 2 and 4 shares per wave, then over launch widths of 4, 12 and
  * 16 waves per CU, each stage on the best of the one before; leaves the
  * fastest setting in the plan and reports it in *best (may be NULL). The

@@ -64,8 +64,8 @@ struct pmp_plan {
   int32_t* status = nullptr;  // device
   pmp::Slot* slots = nullptr;  // device
   uint64_t nslots = 0;
-  int g32 = 8, g64 = 16;
-  uint32_t alpha = 1024;       // per-string work in byte equivalents
+  int g32 = 8, g64 = 8;
+  uint32_t alpha = 768;        // per-string work in byte equivalents
   uint64_t wave_bytes = 8192;  // smallest share of work worth a wave
   int waves_per_cu = 0;        // 0: as many as stay resident
   int shares_per_wave = 1;     // shares of the work per wave (spread over the launch)
@@ -627,7 +627,7 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
   };
   int pairs[16][2];
   const int np = pmp::batch_tile_pairs(pairs, 16);
-  const uint32_t alphas[] = {128, 512, 1024, 2048};
+  const uint32_t alphas[] = {256, 512, 768, 1024, 1536, 2048};
   int r = PMP_OK;
   for (int t = 0; t < np && !r; ++t)
     for (uint32_t al : alphas)
