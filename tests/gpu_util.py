@@ -64,3 +64,17 @@ def oracle_hash(rg, keys_np, flags=0, nthreads=8):
 def first_mismatch(got, want):
     bad = np.nonzero(got != want)[0]
     return None if bad.size == 0 else (int(bad[0]), int(got[bad[0]]), int(want[bad[0]]), int(bad.size))
+
+
+def sample_ragged(rg, idx):
+    """The strings idx of rg (in that order) as a Ragged of their own, for the
+    oracle to hash one by one."""
+    from paper_1609_09840_amd import workloads as W
+
+    idx = np.asarray(idx, dtype=np.int64)
+    lens = rg.offsets[idx + 1] - rg.offsets[idx]
+    off = np.zeros(len(idx) + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    parts = [rg.buf[rg.offsets[i]:rg.offsets[i + 1]] for i in idx]
+    buf = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    return W.Ragged(buf, off, rg.wide)
