@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -43,10 +44,16 @@ DESCR = {
 
 
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the batch kernel's sources with their
+    comments and blank lines removed: edits to comments keep it."""
     h = hashlib.sha256()
     for f in ("pmp_kernels.hip", "pmp_device.hpp", "pmp_internal.h"):
-        with open(os.path.join(ROOT, "paper_1609_09840_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1609_09840_amd", "csrc", f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            line = re.sub(r"//.*$", "", line).rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

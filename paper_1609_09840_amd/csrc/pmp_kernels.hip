@@ -10,8 +10,9 @@
 //  - strings of at most 16 groups of 16 bytes are hashed one per lane out of
 //    the wave's LDS stage, which direct-to-LDS loads fill with their chunks
 //    (coalesced), Algorithm 1 being a single Eq. (1) evaluation for them;
-//  - strings of up to four 128-word blocks, one per group of G lanes, block
-//    by block;
+//  - strings of up to 32 128-word blocks that lie wholly in the share: their
+//    blocks form one task list shared out over the groups of G lanes, the
+//    field elements go to LDS and level 2 is summed by all lanes together;
 //  - longer strings by the whole wave, G lanes per block (a lane owns the
 //    16-byte pieces j, j + G, ... of its block); each block is reduced over
 //    its G lanes, folded into a field element (Sec. 6.2, Algorithm 2) and
@@ -740,10 +741,10 @@ __device__ void locate2(const BatchArgs& B, uint32_t alpha, uint64_t x0, uint64_
 // group t mod (64 / G) at step t / (64 / G), so every group has the same
 // number of blocks whatever the lengths. A block is summed by its group as in
 // block_sum and folded (Sec. 6.2, Algorithm 2); its field element goes to
-// LDS. The next step's block is loaded while the current one is summed. Then
-// one lane per string forms the level-2 value b_2 + sum_c a_{2,c} z_c (Eq. (1)
-// on level 2) from the stored elements. Strings whose tasks do not fit the LDS
-// take a further round. `med` marks lanes whose string (i, o0, len, C1) is
+// LDS with its string's lane and block. The next step's block is loaded while
+// the current one is summed. Then all lanes share the level-2 products
+// a_{2,c} z_c (Eq. (1) on level 2) and each string's lane adds b_2 and folds.
+// Strings whose tasks do not fit the LDS take a further round. `med` marks lanes whose string (i, o0, len, C1) is
 // medium; `zbuf` and `tab` are the wave's stage and table.
 constexpr uint32_t MEDIUM_TASKS = STAGE_BYTES / 16;  // field elements held at once
 static_assert(64 * 4 * 8 <= 4 * STAGE_CHUNKS, "the level-2 limb sums of 64 strings fit the task table");
