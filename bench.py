@@ -121,6 +121,41 @@ def mul_roofline(wl, launch_ms: float) -> dict:
             "frac": round(achieved / peak, 4), "mads_per_launch": mads}
 
 
+def launch_spread(step, plan, batches, stream, n: int = 30) -> dict:
+    """After the timed region: n launches each between its own HIP events
+    (median and p99; the events add a few microseconds to each), and the
+    same launch captured once as a hipGraph and replayed n times back to
+    back (mean)."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    g = pmp.Graph(plan, batches)
+    try:
+        g.launch(stream)  # warm
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        g0.record(stream)
+        for _ in range(n):
+            g.launch(stream)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / n
+    finally:
+        g.close()
+    return {"launches": n, "launch_ms_median": round(float(np.median(t)), 5),
+            "launch_ms_p99": round(float(np.percentile(t, 99)), 5), "graph_replay_ms": round(graph_ms, 5)}
+
+
 def setup(wl, dev):
     import torch
 
@@ -397,6 +432,9 @@ def main():
         "mul_roofline": mul_roofline(wl, launch_ms),
         "paper_context": PAPER_CONTEXT,
     }
+    rec["launch_spread"] = launch_spread(step, plan, [b for b in batches if b is not None], stream)
+    if plan.status() != pmp.PMP_OK:
+        raise RuntimeError("device status not OK after the spread pass")
     if not args.no_plain:
         rec["plain_gpu"] = plain_gpu(keep, dev)
     if not args.no_serve:
