@@ -967,14 +967,23 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
     return;
   }
   const int64_t last = pe.c > 0 ? pe.i : pe.i - 1;  // last string with blocks here
+  // each tile's offsets are loaded while the tile before it is hashed
+  int64_t n0 = 0, n1 = 0;
+  auto tile_offsets = [&](int64_t t0) {
+    const int64_t q = t0 + lane;
+    n0 = 0;
+    n1 = 0;
+    if (q <= last && q < B.count) {
+      n0 = B.offsets[q];
+      n1 = B.offsets[q + 1];
+    }
+  };
+  tile_offsets(ps.i);
   for (int64_t t0 = ps.i; t0 <= last; t0 += 64) {
     const int64_t i = t0 + lane;
     const bool in = i <= last && i < B.count;
-    int64_t o0 = 0, o1 = 0;
-    if (in) {
-      o0 = B.offsets[i];
-      o1 = B.offsets[i + 1];
-    }
+    const int64_t o0 = n0, o1 = n1;
+    if (t0 + 64 <= last) tile_offsets(t0 + 64);
     const bool bad = in && !(o0 >= 0 && o0 <= o1 && (uint64_t)o1 <= B.buf_bytes);
     if (__ballot(bad) && lane == 0)
       __hip_atomic_fetch_or(A.status, STATUS_OFFSETS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1088,28 +1097,32 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(KArgs A) {
         const BatchArgs B = batch_at(A, base + (uint32_t)l);
         const uint64_t lo = x0 > B.work0 ? x0 - B.work0 : 0;
         const uint64_t hi = x1 < B.work0 + B.work ? x1 - B.work0 : B.work;
-        if (B.keys != staged || B.wide != staged_wide) {
-          // this batch's keys into the wave's LDS region
-          __builtin_amdgcn_wave_barrier();  // all lanes done with the previous keys
+        // this batch's keys go to the wave's LDS region; their loads are
+        // issued before the share's search, so that the two overlap
+        const bool restage = B.keys != staged || B.wide != staged_wide;  // uniform
+        uint64_t kv[4] = {0, 0, 0, 0};
+        if (restage) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int e = lane + 64 * q;
-            lk[e] = B.wide ? ((const uint64_t*)B.keys)[e] : ((const uint32_t*)B.keys)[e];
+            kv[q] = B.wide ? ((const uint64_t*)B.keys)[e] : ((const uint32_t*)B.keys)[e];
           }
+        }
+        Pos ps, pe;
+        if (B.wide) locate2<8>(B, A.alpha, lo, hi, ps, pe);
+        else locate2<4>(B, A.alpha, lo, hi, ps, pe);
+        if (restage) {
+          __builtin_amdgcn_wave_barrier();  // all lanes done with the previous keys
+#pragma unroll
+          for (int q = 0; q < 4; ++q) lk[lane + 64 * q] = kv[q];
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           staged = B.keys;
           staged_wide = B.wide;
         }
-        Pos ps, pe;
-        if (B.wide) {
-          locate2<8>(B, A.alpha, lo, hi, ps, pe);
-          run_range<true, G64>(A, B, lk, stage, table, ps, pe);
-        } else {
-          locate2<4>(B, A.alpha, lo, hi, ps, pe);
-          run_range<false, G32>(A, B, lk, stage, table, ps, pe);
-        }
+        if (B.wide) run_range<true, G64>(A, B, lk, stage, table, ps, pe);
+        else run_range<false, G32>(A, B, lk, stage, table, ps, pe);
       }
       if (past) break;
     }
