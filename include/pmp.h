@@ -279,6 +279,46 @@ int pmp_server_replay(pmp_server* server, const pmp_request* reqs, int64_t n, co
 int pmp_server_status(pmp_server* server);
 
 /* ---------------------------------------------------------------------- */
+/* Incremental hashing of ONE string delivered in pieces (Sec. 4: with its
+ * words arriving in order, the tree of Algorithm 1 needs one open node per
+ * level, so a string longer than any buffer, or still being produced, is
+ * hashed in bounded memory). The digest of the pieces appended so far equals
+ * pmp_hash32 / pmp_hash64 of their concatenation, with the same keys and
+ * flags, bit for bit.
+ *
+ * pmp_incr_create: wide = 0 (PM+32) or 1 (PM+64); d_keys is the device key
+ * table (1032 uint32 or uint64), which must stay valid and unchanged for
+ * the object's life. Every call on the object is queued on `stream`, in
+ * order. Allocates about 1.5 KiB of device state plus a workspace (16 bytes
+ * per 64 KiB (PM+32) or 128 KiB (PM+64) of the largest piece). Returns
+ * PMP_E_INVALID_ARG or PMP_E_NOMEM.
+ *
+ * pmp_incr_append: appends nbytes device bytes at d_piece (any alignment;
+ * nbytes = 0 is a no-op). Asynchronous: the piece must stay unchanged until
+ * the stream has passed the call. One launch. A piece larger than any before
+ * (beyond what pmp_incr_reserve set aside) first synchronizes the stream and
+ * grows the workspace. Returns PMP_E_TOO_LONG if the string would need more
+ * than 8 levels (more than 128^8 words after padding), leaving the state as
+ * it was.
+ *
+ * pmp_incr_digest: writes the hash of everything appended so far to d_out
+ * (one output in the layout of pmp_hash32 / pmp_hash64 for these flags).
+ * The state is not changed: more pieces may follow. One launch.
+ *
+ * pmp_incr_reset: starts a new string with the same keys.
+ * pmp_incr_length: bytes appended since creation or the last reset.
+ * pmp_incr_destroy: synchronizes the stream and frees the object (NULL is a
+ * no-op). An object is used by one thread at a time. */
+typedef struct pmp_incr pmp_incr;
+int pmp_incr_create(int wide, const void* d_keys, pmp_stream_t stream, pmp_incr** out);
+int pmp_incr_reserve(pmp_incr* h, uint64_t max_piece_bytes);
+int pmp_incr_append(pmp_incr* h, const uint8_t* d_piece, uint64_t nbytes);
+int pmp_incr_digest(pmp_incr* h, void* d_out, uint32_t flags);
+int pmp_incr_reset(pmp_incr* h);
+int pmp_incr_length(const pmp_incr* h, uint64_t* len);
+int pmp_incr_destroy(pmp_incr* h);
+
+/* ---------------------------------------------------------------------- */
 /* Plain GPU form, kept as a baseline: one string at a time, one launch per
  * tree level, one thread per block of 128 words. h_offsets is a HOST copy of
  * the offsets (the baseline needs the lengths on the host to size its

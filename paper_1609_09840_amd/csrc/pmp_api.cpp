@@ -708,4 +708,172 @@ int pmp_probe_mad_rate(double* mads_per_s) {
   return PMP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Incremental hashing: the host keeps the byte count, from which every count
+// the kernels need follows (blocks completed, nodes per level, carried bytes).
+}  // extern "C"
+
+struct pmp_incr {
+  int wide = 0;
+  const void* keys = nullptr;
+  hipStream_t stream = nullptr;
+  pmp::IncrState* st = nullptr;  // device state, followed by the two boundary sums
+  uint64_t* sums = nullptr;
+  uint4* z = nullptr;            // two level-output buffers of cap entries each
+  uint64_t cap = 0;
+  uint64_t len = 0;              // bytes appended since creation or reset
+};
+
+namespace {
+
+// level-2 nodes an append of n bytes can touch, plus room for the open ends
+uint64_t incr_nodes_for(const pmp_incr* h, uint64_t n) {
+  const uint64_t C = (uint64_t)PMP_BLOCK * (h->wide ? 8 : 4);
+  return n / (C * PMP_BLOCK) + 2;
+}
+
+int incr_grow(pmp_incr* h, uint64_t entries) {
+  if (entries <= h->cap) return PMP_OK;
+  // queued appends may still use the old buffers
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (h->z) {
+    e = hipFree(h->z);
+    h->z = nullptr;
+    h->cap = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+  }
+  e = hipMalloc((void**)&h->z, 2 * entries * sizeof(uint4));
+  if (e != hipSuccess) {
+    h->z = nullptr;
+    return fail(PMP_E_NOMEM, "incremental workspace of %llu bytes: %s",
+                (unsigned long long)(2 * entries * sizeof(uint4)), hipGetErrorString(e));
+  }
+  h->cap = entries;
+  return PMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmp_incr_create(int wide, const void* d_keys, pmp_stream_t stream, pmp_incr** out) {
+  if (!out) return fail(PMP_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d_keys) return fail(PMP_E_INVALID_ARG, "d_keys is NULL");
+  if (wide != 0 && wide != 1) return fail(PMP_E_INVALID_ARG, "wide must be 0 (PM+32) or 1 (PM+64)");
+  pmp_incr* h = new pmp_incr;
+  h->wide = wide;
+  h->keys = d_keys;
+  h->stream = (hipStream_t)stream;
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, sizeof(pmp::IncrState) + 8 * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    delete h;
+    return fail(PMP_E_NOMEM, "incremental state: %s", hipGetErrorString(e));
+  }
+  h->st = (pmp::IncrState*)mem;
+  h->sums = (uint64_t*)((char*)mem + sizeof(pmp::IncrState));
+  int r = incr_grow(h, incr_nodes_for(h, 0));
+  if (r == PMP_OK) {
+    e = pmp::launch_incr_reset(h->st, h->stream);
+    if (e != hipSuccess) r = hip_fail(e, "state reset");
+  }
+  if (r != PMP_OK) {
+    (void)hipFree(h->z);
+    (void)hipFree(h->st);
+    delete h;
+    return r;
+  }
+  *out = h;
+  return PMP_OK;
+}
+
+int pmp_incr_reserve(pmp_incr* h, uint64_t max_piece_bytes) {
+  if (!h) return fail(PMP_E_INVALID_ARG, "handle is NULL");
+  return incr_grow(h, incr_nodes_for(h, max_piece_bytes));
+}
+
+int pmp_incr_append(pmp_incr* h, const uint8_t* d_piece, uint64_t nbytes) {
+  if (!h) return fail(PMP_E_INVALID_ARG, "handle is NULL");
+  if (nbytes == 0) return PMP_OK;
+  if (!d_piece) return fail(PMP_E_INVALID_ARG, "d_piece is NULL");
+  const uint64_t C = (uint64_t)PMP_BLOCK * (h->wide ? 8 : 4);
+  // the padded string may have at most 128^8 words: 128^7 blocks
+  const uint64_t max_blocks = 1ull << 49;
+  if (nbytes > (1ull << 62) || h->len + nbytes < h->len || (h->len + nbytes) / C + 1 > max_blocks)
+    return fail(PMP_E_TOO_LONG, "the string would need more than %d levels", PMP_LEVELS);
+  if (nbytes / (C * PMP_BLOCK) + 2 > 0x7fffffffull)
+    return fail(PMP_E_INVALID_ARG, "piece of %llu bytes: append it in smaller pieces", (unsigned long long)nbytes);
+  const uint64_t len1 = h->len + nbytes;
+  const uint64_t s1 = h->len / C, k = len1 / C - s1;
+  const uint32_t t = (uint32_t)(h->len % C);
+  hipError_t e;
+  if (k == 0) {
+    e = pmp::launch_incr_carry(h->st, t, d_piece, (int64_t)nbytes, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "carry launch");
+  } else {
+    const uint64_t nwg = (s1 + k - 1) / PMP_BLOCK - s1 / PMP_BLOCK + 1;
+    int r = incr_grow(h, nwg + 2);
+    if (r != PMP_OK) return r;
+    pmp::IncrArgs a{};
+    a.piece = d_piece;
+    a.n = (int64_t)nbytes;
+    a.s1 = s1;
+    a.k = k;
+    a.t = t;
+    a.r_new = (uint32_t)(len1 % C);
+    a.nwg = (uint32_t)nwg;
+    a.keys = h->keys;
+    a.st = h->st;
+    a.za = h->z;
+    a.zb = h->z + h->cap;
+    a.sums = h->sums;
+    e = pmp::launch_incr_append(h->wide, a, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "append launch");
+  }
+  h->len = len1;
+  return PMP_OK;
+}
+
+int pmp_incr_digest(pmp_incr* h, void* d_out, uint32_t flags) {
+  if (!h) return fail(PMP_E_INVALID_ARG, "handle is NULL");
+  if (!d_out) return fail(PMP_E_INVALID_ARG, "d_out is NULL");
+  if (flags & ~(PMP_NO_MIX | PMP_OUT_FIELD)) return fail(PMP_E_INVALID_ARG, "unknown flag bits");
+  const uint64_t C = (uint64_t)PMP_BLOCK * (h->wide ? 8 : 4);
+  uint64_t nodes[PMP_LEVELS + 1] = {0};
+  nodes[1] = h->len / C + 1;  // the open block holds at least the pad word
+  for (int j = 2; j <= PMP_LEVELS; ++j) nodes[j] = (nodes[j - 1] + PMP_BLOCK - 1) / PMP_BLOCK;
+  hipError_t e = pmp::launch_incr_digest(h->wide, h->st, (uint32_t)(h->len % C), nodes, h->keys, d_out, flags,
+                                         h->stream);
+  if (e != hipSuccess) return hip_fail(e, "digest launch");
+  return PMP_OK;
+}
+
+int pmp_incr_reset(pmp_incr* h) {
+  if (!h) return fail(PMP_E_INVALID_ARG, "handle is NULL");
+  hipError_t e = pmp::launch_incr_reset(h->st, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "state reset");
+  h->len = 0;
+  return PMP_OK;
+}
+
+int pmp_incr_length(const pmp_incr* h, uint64_t* len) {
+  if (!h || !len) return fail(PMP_E_INVALID_ARG, "NULL argument");
+  *len = h->len;
+  return PMP_OK;
+}
+
+int pmp_incr_destroy(pmp_incr* h) {
+  if (!h) return PMP_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  hipError_t e1 = hipFree(h->z);
+  hipError_t e2 = hipFree(h->st);
+  delete h;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+  return PMP_OK;
+}
+
 }  // extern "C"

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pmp.h"
+
 namespace pmp {
 
 typedef unsigned __int128 u128;
@@ -196,6 +198,44 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z *= 0xc4ceb9fe1a85ec53ull;
   z ^= z >> 33;
   return z;
+}
+
+// ---------------------------------------------------------------------------
+// The two variants: key and block-sum types, word size W in bytes.
+template <bool WIDE>
+struct Tr;
+template <>
+struct Tr<false> {
+  using key_t = uint32_t;
+  using Sum = S32;
+  static constexpr int W = 4;
+};
+template <>
+struct Tr<true> {
+  using key_t = uint64_t;
+  using Sum = S64;
+  static constexpr int W = 8;
+};
+
+// Output i (Sec. 5: h mod 2^n; the Sec. 7 mixer unless PMP_NO_MIX; or, with
+// PMP_OUT_FIELD, the field value itself)
+template <bool WIDE>
+__device__ __forceinline__ void store_value(void* out, uint32_t flags, int64_t i, const Fe& z) {
+  if (flags & PMP_OUT_FIELD) {
+    uint64_t* o = (uint64_t*)out;
+    if (WIDE) {
+      o[2 * i] = z.lo;
+      o[2 * i + 1] = z.hi;
+    } else {
+      o[i] = z.lo | ((uint64_t)z.hi << 32);
+    }
+  } else if (WIDE) {
+    uint64_t r = z.lo;
+    ((uint64_t*)out)[i] = (flags & PMP_NO_MIX) ? r : mix64(r);
+  } else {
+    uint32_t r = (uint32_t)z.lo;
+    ((uint32_t*)out)[i] = (flags & PMP_NO_MIX) ? r : mix32(r);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,365 @@
+// Incremental hashing of one string that arrives in pieces (Sec. 4: the tree
+// of Algorithm 1 needs only one open node per level when its words arrive in
+// order, so a string of any length is hashed in bounded memory).
+//
+// The state (IncrState) keeps the bytes of the open level-1 block and, for
+// each level j >= 2, the exact sum over the values already produced for the
+// open level-j node. Because Eq. (1) is a sum of products, the values need not
+// be kept: each is multiplied by its key as soon as it exists.
+//
+// An append that completes level-1 blocks is one launch. Workgroup w builds
+// level-2 node s1 / 128 + w out of the blocks of the piece that fall in it:
+// 32 groups of 8 lanes, a group per block at a time, each lane owning the
+// 16-byte pieces j, j + 8, ... of the block (its level-1 keys stay in
+// registers). A block is summed exactly over its 8 lanes, folded into a field
+// element (Sec. 6.2 and Algorithm 2) and multiplied by its level-2 key. A node
+// whose blocks all lie in the piece is finished by its workgroup. The last
+// workgroup to finish (a device-scope counter) completes the first and last
+// level-2 nodes with the state's open sums, stores the new open sums and
+// carried bytes, and climbs the levels above 2, which hold at most 1/128 of
+// the level-2 values.
+//
+// A digest pads the open block (end of Sec. 4), hashes it and climbs through
+// the open nodes to the root: the do-while of Algorithm 1 stops at the first
+// level with a single node. It reads the state without changing it, so more
+// pieces may follow.
+#include "pmp_device.hpp"
+#include "pmp_internal.h"
+
+namespace pmp {
+
+namespace {
+
+constexpr int GL = 8;  // lanes per level-1 block
+
+__device__ __forceinline__ const uint8_t* gp(uint64_t a) {
+  return (const uint8_t*)(const __attribute__((address_space(1))) uint8_t*)(uintptr_t)a;
+}
+
+__device__ __forceinline__ void to_words(const S32& s, uint64_t* w) {
+  w[0] = s.lo;
+  w[1] = s.hi;
+  w[2] = 0;
+}
+__device__ __forceinline__ void to_words(const S64& s, uint64_t* w) {
+  w[0] = s.w0;
+  w[1] = s.w1;
+  w[2] = s.w2;
+}
+__device__ __forceinline__ void from_words(S32& s, const uint64_t* w) {
+  s.lo = w[0];
+  s.hi = (uint32_t)w[1];
+}
+__device__ __forceinline__ void from_words(S64& s, const uint64_t* w) {
+  s.w0 = w[0];
+  s.w1 = w[1];
+  s.w2 = (uint32_t)w[2];
+}
+__device__ __forceinline__ uint4 pack(const Fe& z) {
+  return make_uint4((uint32_t)z.lo, (uint32_t)(z.lo >> 32), z.hi, 0u);
+}
+__device__ __forceinline__ Fe unpack(const uint4& v) {
+  Fe z;
+  z.lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
+  z.hi = v.z;
+  return z;
+}
+
+// Level j >= 2 node value from its exact sum: add b_j, reduce (Eq. (1)).
+template <bool WIDE>
+__device__ __forceinline__ Fe finish(typename Tr<WIDE>::Sum S, const typename Tr<WIDE>::key_t* keys, int j) {
+  add_word(S, (uint64_t)keys[LMAX * BLOCK + (j - 1)]);
+  return reduce(S);
+}
+
+// One climb step inside a workgroup: the n_in new level-(j-1) values in[],
+// numbered s_in .. s_in + n_in - 1 within their level, go into the level-j
+// nodes; complete nodes are written to out[] in order, the open one (if any)
+// goes to part[j]. Returns the number of values written.
+template <bool WIDE>
+__device__ uint64_t climb(IncrState* st, const typename Tr<WIDE>::key_t* keys, int j, const uint4* in,
+                          uint64_t n_in, uint64_t s_in, uint4* out, uint64_t* pend) {
+  using S = typename Tr<WIDE>::Sum;
+  const uint64_t q0 = s_in / BLOCK, q1 = (s_in + n_in - 1) / BLOCK;
+  const bool start_open = s_in % BLOCK != 0;
+  const bool end_open = (s_in + n_in) % BLOCK != 0;
+  S old;
+  from_words(old, st->part[j]);
+  const typename Tr<WIDE>::key_t* a = keys + (j - 1) * BLOCK;
+  for (uint64_t q = q0 + threadIdx.x; q <= q1; q += blockDim.x) {
+    const uint64_t lo = q * BLOCK > s_in ? q * BLOCK : s_in;
+    const uint64_t hi = q * BLOCK + BLOCK < s_in + n_in ? q * BLOCK + BLOCK : s_in + n_in;
+    S acc;
+    zero(acc);
+    for (uint64_t c = lo; c < hi; ++c) mac_fe(acc, a[c % BLOCK], unpack(in[c - s_in]));
+    if (q == q0 && start_open) add(acc, old);
+    if (hi == q * BLOCK + BLOCK) out[q - q0] = pack(finish<WIDE>(acc, keys, j));
+    else to_words(acc, pend);  // the last node, still open
+  }
+  __syncthreads();  // every reader of part[j] is done
+  if (threadIdx.x == 0) {
+    uint64_t* p = st->part[j];
+    if (end_open) {
+      p[0] = pend[0];
+      p[1] = pend[1];
+      p[2] = pend[2];
+    } else {
+      p[0] = p[1] = p[2] = 0;
+    }
+  }
+  __syncthreads();  // out[] and part[j] are visible to the whole workgroup
+  return (s_in + n_in) / BLOCK - q0;
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
+  using T = Tr<WIDE>;
+  using S = typename T::Sum;
+  using K = typename T::key_t;
+  constexpr int W = T::W;
+  constexpr int C = BLOCK * W;        // bytes per level-1 block
+  constexpr int NG = C / (16 * GL);   // 16-byte pieces per lane and block
+  constexpr int KPG = 16 / W;         // words per 16-byte piece
+  __shared__ uint32_t stg[C / 4];     // the block that begins in the carried bytes
+  __shared__ uint64_t red[256 / GL][3];
+  __shared__ uint64_t pend[3];
+  __shared__ uint32_t is_last;
+
+  const K* keys = (const K*)A.keys;
+  const int tid = (int)threadIdx.x, g = tid / GL, j = tid % GL;
+  const uint64_t q = A.s1 / BLOCK + blockIdx.x;  // this workgroup's level-2 node
+  const uint64_t c_lo = q * BLOCK > A.s1 ? q * BLOCK : A.s1;
+  const uint64_t c_hi = q * BLOCK + BLOCK < A.s1 + A.k ? q * BLOCK + BLOCK : A.s1 + A.k;
+
+  if (blockIdx.x == 0 && A.t > 0) {  // carried bytes, then the piece's first bytes
+    uint8_t* s8 = (uint8_t*)stg;
+    const uint8_t* cb = (const uint8_t*)A.st->carry;
+    for (int p = tid; p < C; p += 256) s8[p] = p < (int)A.t ? cb[p] : A.piece[p - (int)A.t];
+    __syncthreads();
+  }
+
+  // level-1 keys of this lane's pieces: word KPG (GL u + j) + v
+  K kk[NG * KPG];
+#pragma unroll
+  for (int u = 0; u < NG; ++u)
+#pragma unroll
+    for (int v = 0; v < KPG; ++v) kk[KPG * u + v] = keys[KPG * (GL * u + j) + v];
+  const uint64_t b1 = (uint64_t)keys[LMAX * BLOCK];
+  const K* a2 = keys + BLOCK;
+
+  // every block of the piece shares one byte misalignment
+  const uint64_t base = (uint64_t)(uintptr_t)A.piece - A.t;
+  const uint32_t sh = (uint32_t)(base & 3u);
+
+  S node;
+  zero(node);
+  for (uint64_t c = q * BLOCK + g; c < c_hi; c += 256 / GL) {
+    if (c < c_lo) continue;
+    const uint64_t i = c - A.s1;  // block index within the piece
+    uint32_t d[NG][5];
+    uint32_t s_eff = sh;
+    if (i == 0 && A.t > 0) {
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        const uint32_t* p = stg + 4 * (GL * u + j);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[u][v] = p[v];
+        d[u][4] = 0;
+      }
+      s_eff = 0;
+    } else {
+      // the aligned dwords that hold the block; the one past its end only
+      // when the block is misaligned (it then holds the block's last bytes)
+      const uint64_t a4 = (base + i * C) & ~3ull;
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        const uint8_t* p = gp(a4 + 16 * (uint64_t)(GL * u + j));
+        Q x = load16(p);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[u][v] = x.d[v];
+        d[u][4] = sh ? *(const uint32_t*)__builtin_assume_aligned(p + 16, 4) : 0u;
+      }
+    }
+    S s;
+    if constexpr (WIDE) {
+      P64 p;
+      zero(p);
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        uint32_t x[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = align_bytes(d[u][v + 1], d[u][v], s_eff);
+        mac64_vv(p, kk[2 * u], x[0], x[1]);
+        mac64_vv(p, kk[2 * u + 1], x[2], x[3]);
+      }
+      s = collapse(p);
+    } else {
+      zero(s);
+#pragma unroll
+      for (int u = 0; u < NG; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) mac_vv(s.lo, s.hi, kk[4 * u + v], align_bytes(d[u][v + 1], d[u][v], s_eff));
+    }
+    group_sum<GL>(s);  // the block's exact sum, in every lane of the group
+    add_word(s, b1);
+    mac_fe(node, a2[c % BLOCK], reduce(s));
+  }
+  if (j == 0) to_words(node, red[g]);
+  __syncthreads();
+
+  if (tid == 0) {
+    S tot;
+    zero(tot);
+    for (int h = 0; h < 256 / GL; ++h) {
+      S x;
+      from_words(x, red[h]);
+      add(tot, x);
+    }
+    if (c_lo == q * BLOCK && c_hi == q * BLOCK + BLOCK) {
+      A.za[blockIdx.x] = pack(finish<WIDE>(tot, keys, 2));  // a whole node
+    } else {
+      to_words(tot, A.sums + 4 * (blockIdx.x == 0 ? 0 : 1));  // first or last node, open
+    }
+    __threadfence();  // release this workgroup's results
+    const uint32_t prev = atomicAdd(&A.st->done, 1u);
+    is_last = prev == A.nwg - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();  // acquire the other workgroups' results
+
+  // level 2: the nodes that this piece shares with the string before or
+  // after it
+  if (tid == 0) {
+    IncrState* st = A.st;
+    const bool start_open = A.s1 % BLOCK != 0;
+    const bool end_open = (A.s1 + A.k) % BLOCK != 0;
+    const bool one = A.nwg == 1;
+    uint64_t np[3] = {0, 0, 0};
+    if (start_open || (one && end_open)) {
+      S x;
+      from_words(x, A.sums);
+      if (start_open) {
+        S o;
+        from_words(o, st->part[2]);
+        add(x, o);
+      }
+      if (!(one && end_open)) A.za[0] = pack(finish<WIDE>(x, keys, 2));
+      else to_words(x, np);
+    }
+    if (!one && end_open) {
+      np[0] = A.sums[4];
+      np[1] = A.sums[5];
+      np[2] = A.sums[6];
+    }
+    st->part[2][0] = np[0];
+    st->part[2][1] = np[1];
+    st->part[2][2] = np[2];
+    st->done = 0;  // ready for the next append
+  }
+  // the bytes carried to the next piece (block 0's reader has finished)
+  {
+    uint8_t* cb = (uint8_t*)A.st->carry;
+    const uint8_t* src = A.piece + (A.n - (int64_t)A.r_new);
+    for (uint32_t p = (uint32_t)tid; p < A.r_new; p += 256) cb[p] = src[p];
+  }
+  __syncthreads();
+
+  // levels 3 and up
+  uint64_t n_in = (A.s1 + A.k) / BLOCK - A.s1 / BLOCK;  // complete level-2 nodes
+  uint64_t s_in = A.s1 / BLOCK;                         // level-2 values before this piece
+  uint4* in = A.za;
+  uint4* out = A.zb;
+  for (int lvl = 3; lvl <= LMAX && n_in > 0; ++lvl) {
+    const uint64_t n_out = climb<WIDE>(A.st, keys, lvl, in, n_in, s_in, out, pend);
+    s_in /= BLOCK;
+    n_in = n_out;
+    uint4* t = in;
+    in = out;
+    out = t;
+  }
+}
+
+// An append that completes no block: its bytes join the carried ones.
+__global__ void incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, int64_t n) {
+  uint8_t* cb = (uint8_t*)st->carry;
+  for (int64_t p = threadIdx.x; p < n; p += blockDim.x) cb[t + p] = piece[p];
+}
+
+// Digest, one wave: lane l forms words 2l and 2l + 1 of the padded open block
+// (t carried bytes, a byte 0x01, zeros), then the climb. nodes[j] is the
+// number of level-j nodes of the whole string (level 1: blocks).
+struct Nodes {
+  uint64_t n[LMAX + 1];
+};
+template <bool WIDE>
+__global__ void incr_digest(const IncrState* st, uint32_t t, Nodes N, const void* keysv, void* out, uint32_t flags) {
+  using T = Tr<WIDE>;
+  using S = typename T::Sum;
+  using K = typename T::key_t;
+  const K* keys = (const K*)keysv;
+  const int lane = (int)threadIdx.x;
+  S s;
+  zero(s);
+  if constexpr (WIDE) {
+    P64 p;
+    zero(p);
+    for (int v = 0; v < 2; ++v) {
+      const int w = 2 * lane + v;
+      uint32_t x0 = st->carry[2 * w], x1 = st->carry[2 * w + 1];
+      tail_word64(x0, x1, (int64_t)t - 8 * w);
+      mac64_vv(p, keys[w], x0, x1);
+    }
+    s = collapse(p);
+  } else {
+    for (int v = 0; v < 2; ++v) {
+      const int w = 2 * lane + v;
+      mac_vv(s.lo, s.hi, keys[w], tail_word32(st->carry[w], (int64_t)t - 4 * w));
+    }
+  }
+  reduce_lanes(s, 1, 64);
+  if (lane != 0) return;
+  add_word(s, (uint64_t)keys[LMAX * BLOCK]);
+  Fe z = reduce(s);
+  for (int j = 1; j < LMAX && N.n[j] > 1; ++j) {
+    S acc;
+    from_words(acc, st->part[j + 1]);
+    mac_fe(acc, keys[j * BLOCK + (N.n[j] - 1) % BLOCK], z);
+    z = finish<WIDE>(acc, keys, j + 1);
+  }
+  store_value<WIDE>(out, flags, 0, z);
+}
+
+__global__ void incr_reset(IncrState* st) {
+  uint64_t* w = (uint64_t*)st;
+  for (uint32_t i = threadIdx.x; i < sizeof(IncrState) / 8; i += blockDim.x) w[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_incr_append(int wide, const IncrArgs& a, hipStream_t s) {
+  if (wide) hipLaunchKernelGGL(incr_append<true>, dim3(a.nwg), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(incr_append<false>, dim3(a.nwg), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(incr_carry, dim3(1), dim3(256), 0, s, st, t, piece, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_incr_digest(int wide, const IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
+                              void* out, uint32_t flags, hipStream_t s) {
+  Nodes N;
+  for (int j = 0; j <= LMAX; ++j) N.n[j] = nodes[j];
+  if (wide) hipLaunchKernelGGL(incr_digest<true>, dim3(1), dim3(64), 0, s, st, t, N, keys, out, flags);
+  else hipLaunchKernelGGL(incr_digest<false>, dim3(1), dim3(64), 0, s, st, t, N, keys, out, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_incr_reset(IncrState* st, hipStream_t s) {
+  hipLaunchKernelGGL(incr_reset, dim3(1), dim3(256), 0, s, st);
+  return hipGetLastError();
+}
+
+}  // namespace pmp

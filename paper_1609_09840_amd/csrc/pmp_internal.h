@@ -55,6 +55,42 @@ struct KArgs {
   uint64_t share;        // work per share
 };
 
+// Incremental hashing of one string delivered in pieces (the streaming form
+// of Algorithm 1: one open node per level, Sec. 4). Device-resident; all
+// zero after creation and reset.
+//   part[j] (j = 2..8): exact sum sum_i a_{j,i} z_i over the level-(j-1)
+//     values z already produced for the open level-j node (b_j not added);
+//     3 words (PM+32: lo, hi, 0; PM+64: w0, w1, w2), the fourth unused.
+//   carry: the bytes of the open level-1 block (fewer than 128 W).
+//   done: workgroups of the running append that have finished (0 between
+//     launches).
+struct IncrState {
+  uint64_t part[9][4];
+  uint32_t done;
+  uint32_t pad_[3];
+  uint32_t carry[(1024 + 16) / 4];
+};
+
+// One append that completes at least one level-1 block. The piece's bytes
+// follow the t carried bytes; blocks s1 .. s1 + k - 1 (numbered from the
+// string's start) are completed by it; r_new bytes are carried afterwards.
+// Workgroup w builds level-2 node s1 / 128 + w.
+struct IncrArgs {
+  const uint8_t* piece;
+  int64_t n;
+  uint64_t s1;
+  uint64_t k;
+  uint32_t t;
+  uint32_t r_new;
+  uint32_t nwg;
+  uint32_t pad_;
+  const void* keys;
+  IncrState* st;
+  uint4* za;       // level outputs, ping-pong: each nwg + 2 entries
+  uint4* zb;
+  uint64_t* sums;  // raw sums of the first and last level-2 nodes (2 x 4 words)
+};
+
 // host side (pmp_api.cpp)
 int set_error(int code, const char* msg);  // sets the message pmp_last_error returns
 int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream);
@@ -67,6 +103,11 @@ int batch_tile_pairs(int (*pairs)[2], int max);  // list them; returns how many
 hipError_t launch_plain_string(int wide, const uint8_t* buf, uint64_t buf_bytes, int64_t o0, int64_t len,
                                const void* keys, void* out, int64_t index, uint32_t flags, uint4* scratch,
                                uint64_t scratch_slots, hipStream_t s);
+hipError_t launch_incr_append(int wide, const IncrArgs& a, hipStream_t s);
+hipError_t launch_incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, int64_t n, hipStream_t s);
+hipError_t launch_incr_digest(int wide, const IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
+                              void* out, uint32_t flags, hipStream_t s);
+hipError_t launch_incr_reset(IncrState* st, hipStream_t s);
 hipError_t launch_debug_fold(int wide, const void* w0, const void* w1, const uint32_t* w2, void* z, int64_t n,
                              hipStream_t s);
 

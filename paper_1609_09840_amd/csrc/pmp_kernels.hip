@@ -31,21 +31,6 @@
 
 namespace pmp {
 
-template <bool WIDE>
-struct Tr;
-template <>
-struct Tr<false> {
-  using key_t = uint32_t;
-  using Sum = S32;
-  static constexpr int W = 4;
-};
-template <>
-struct Tr<true> {
-  using key_t = uint64_t;
-  using Sum = S64;
-  static constexpr int W = 8;
-};
-
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
@@ -77,24 +62,9 @@ __device__ __forceinline__ uint64_t wave_excl_scan(uint64_t v, uint64_t* total) 
 }
 
 // ---------------------------------------------------------------------------
-// Output (Sec. 5: h mod 2^n; Sec. 7 mixer unless NO_MIX; or the field value)
 template <bool WIDE>
 __device__ __forceinline__ void store_out(const BatchArgs& B, int64_t i, const Fe& z) {
-  if (B.flags & FLAG_OUT_FIELD) {
-    uint64_t* o = (uint64_t*)B.out;
-    if (WIDE) {
-      o[2 * i] = z.lo;
-      o[2 * i + 1] = z.hi;
-    } else {
-      o[i] = z.lo | ((uint64_t)z.hi << 32);
-    }
-  } else if (WIDE) {
-    uint64_t r = z.lo;
-    ((uint64_t*)B.out)[i] = (B.flags & FLAG_NO_MIX) ? r : mix64(r);
-  } else {
-    uint32_t r = (uint32_t)z.lo;
-    ((uint32_t*)B.out)[i] = (B.flags & FLAG_NO_MIX) ? r : mix32(r);
-  }
+  store_value<WIDE>(B.out, B.flags, i, z);
 }
 
 // ---------------------------------------------------------------------------

@@ -140,6 +140,13 @@ def _load():
         "pmp_server_status": [vp],
         "pmp_hash_plain": [i32, vp, u64, vp, i64, vp, vp, u32, vp, u64, vp],
         "pmp_debug_fold": [i32, vp, vp, vp, vp, i64, vp],
+        "pmp_incr_create": [i32, vp, vp, ctypes.POINTER(vp)],
+        "pmp_incr_reserve": [vp, u64],
+        "pmp_incr_append": [vp, vp, u64],
+        "pmp_incr_digest": [vp, vp, u32],
+        "pmp_incr_reset": [vp],
+        "pmp_incr_length": [vp, ctypes.POINTER(u64)],
+        "pmp_incr_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -360,6 +367,68 @@ def _host_ptr(a: np.ndarray, name: str):
     if not a.flags["C_CONTIGUOUS"]:
         raise ValueError(f"{name} must be C-contiguous")
     return a.ctypes.data if a.size else 0
+
+
+class Incr:
+    """Incremental hash of one string appended in pieces (pmp_incr_*): the
+    digest of the pieces so far equals pmp_hash32/64 of their concatenation.
+    keys: device key table (uint32 or uint64 [1032]); every call is queued on
+    `stream` (default: the current stream when the object is made)."""
+
+    def __init__(self, wide: bool, keys, stream=None):
+        import torch
+
+        if keys.dtype != (torch.uint64 if wide else torch.uint32) or keys.numel() != PMP_KEYS:
+            raise ValueError("keys must be a device tensor of 1032 uint32 (PM+32) or uint64 (PM+64)")
+        self.wide = bool(wide)
+        self.keys = keys  # kept alive: the library holds its pointer
+        self.device = keys.device
+        h = ctypes.c_void_p()
+        _check(_lib.pmp_incr_create(int(wide), _dev_ptr(keys, "keys"), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def reserve(self, max_piece_bytes: int):
+        _check(_lib.pmp_incr_reserve(self.handle, max_piece_bytes))
+
+    def append(self, piece, nbytes: int | None = None):
+        """Append a device uint8 tensor (or `nbytes` bytes at its start). The
+        tensor must stay unchanged until the stream has passed the call."""
+        n = piece.numel() if nbytes is None else int(nbytes)
+        if n > piece.numel():
+            raise ValueError("nbytes exceeds the tensor")
+        p = _dev_ptr(piece, "piece") if n else ctypes.c_void_p(0)
+        _check(_lib.pmp_incr_append(self.handle, p, n))
+
+    def digest(self, out=None, flags: int = 0):
+        """Hash of everything appended so far (one output, layout as for
+        pmp_hash32/64 with these flags); the state is kept."""
+        if out is None:
+            out = _out_for(self.wide, 1, flags, self.device)
+        _check(_lib.pmp_incr_digest(self.handle, _dev_ptr(out, "out"), flags))
+        return out
+
+    def reset(self):
+        _check(_lib.pmp_incr_reset(self.handle))
+
+    def __len__(self):
+        v = ctypes.c_uint64()
+        _check(_lib.pmp_incr_length(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(_lib.pmp_incr_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pmp_incr_create(wide: bool, keys, stream=None) -> Incr:
+    return Incr(wide, keys, stream)
 
 
 class Server:
