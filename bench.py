@@ -14,7 +14,10 @@ Prints ONE JSON line. Besides the headline value it carries:
                 rocprofv3 counter summary when it was taken on the current
                 kernel source, else null;
   cpu_baseline  the CPU oracle on a bounded sample of the same workload;
-  plain_gpu     the one-string-per-launch GPU form on a prefix of the batch.
+  plain_gpu     the one-string-per-launch GPU form on a prefix of the batch;
+  incremental   one 1 GiB string hashed through pmp_incr_* in pieces of
+                1 MiB, 16 MiB and 256 MiB (both variants), checked equal to
+                the batched path's hash of the same string.
 """
 from __future__ import annotations
 
@@ -256,6 +259,50 @@ def plain_gpu(keep, dev, max_strings: int = 4000):
             "sample": f"first {nstr} strings of the batch ({tot_bytes} bytes), same outputs as the batched path"}
 
 
+def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20), reps: int = 3) -> dict:
+    """One string of `total` bytes appended in equal pieces, then a digest;
+    HIP events on the object's stream around `reps` whole passes (reset,
+    appends, digest). The digest must equal pmp_hash32/64 of the string."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(909)
+    data = torch.randint(0, 256, (total,), dtype=torch.uint8, device=dev, generator=g)
+    off = torch.tensor([0, total], dtype=torch.int64, device=dev)
+    res = {"string_bytes": total, "unit": "GB/s", "runs": []}
+    for wide in (False, True):
+        kn = pmp.pmp_expand_keys64(2) if wide else pmp.pmp_expand_keys32(1)
+        keys = torch.from_numpy(kn.view(np.int64) if wide else kn.view(np.int32)).to(dev)
+        keys = keys.view(torch.uint64 if wide else torch.uint32)
+        ref = (pmp.pmp_hash64 if wide else pmp.pmp_hash32)(data, off, keys)
+        h = pmp.Incr(wide, keys)
+        h.reserve(max(pieces))
+        for piece in pieces:
+            def one_pass():
+                h.reset()
+                for o in range(0, total, piece):
+                    h.append(data[o:o + piece])
+                return h.digest()
+            d = one_pass()  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                d = one_pass()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if not torch.equal(d, ref):
+                raise RuntimeError("incremental digest disagrees with the batched path")
+            gbs = total / (ms * 1e-3) / 1e9
+            res["runs"].append({"variant": "PM+64" if wide else "PM+32", "piece_bytes": piece,
+                                "appends": -(-total // piece), "ms": round(ms, 4), "value": round(gbs, 1),
+                                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        h.close()
+    return res
+
+
 def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505, per_launch: int = 16,
                   sat_passes: int = 8):
     """Serving workload: Poisson arrivals of requests of 1..4096 strings with
@@ -327,6 +374,11 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0, help="waves per CU (0: as many as stay resident)")
     ap.add_argument("--alpha", type=int, default=0, help="per-string work weight in bytes (0: default)")
     ap.add_argument("--shares", type=int, default=0, help="shares of the work per wave (0: default)")
+    ap.add_argument("--no-incr", action="store_true", help="skip the incremental (one string in pieces) pass")
+    ap.add_argument("--incr-only", action="store_true",
+                    help="only run the incremental pass and print its JSON (for profiling its kernels)")
+    ap.add_argument("--incr-pieces", default="1048576,16777216,268435456",
+                    help="piece sizes of the incremental pass, in bytes, comma-separated")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -349,6 +401,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.calibrate_copy, "launches": 5}), flush=True)
+        return
+    incr_pieces = tuple(int(x) for x in args.incr_pieces.split(",") if x)
+    if args.incr_only:
+        print(json.dumps({"incremental": incremental(dev, pieces=incr_pieces)}), flush=True)
         return
     wl = W.CONFIGS[args.config]()
     keep, batches = setup(wl, dev)
@@ -439,6 +495,8 @@ def main():
         rec["plain_gpu"] = plain_gpu(keep, dev)
     if not args.no_serve:
         rec["serving"] = serving_sweep(dev)
+    if not args.no_incr:
+        rec["incremental"] = incremental(dev, pieces=incr_pieces)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

@@ -295,7 +295,8 @@ int pmp_server_status(pmp_server* server);
  *
  * pmp_incr_append: appends nbytes device bytes at d_piece (any alignment;
  * nbytes = 0 is a no-op). Asynchronous: the piece must stay unchanged until
- * the stream has passed the call. One launch. A piece larger than any before
+ * the stream has passed the call. Two launches (one when the piece completes
+ * no 128-word block: its bytes are only carried). A piece larger than any before
  * (beyond what pmp_incr_reserve set aside) first synchronizes the stream and
  * grows the workspace. Returns PMP_E_TOO_LONG if the string would need more
  * than 8 levels (more than 128^8 words after padding), leaving the state as

@@ -719,17 +719,23 @@ struct pmp_incr {
   hipStream_t stream = nullptr;
   pmp::IncrState* st = nullptr;  // device state, followed by the two boundary sums
   uint64_t* sums = nullptr;
-  uint4* z = nullptr;            // two level-output buffers of cap entries each
+  uint4* z = nullptr;            // two level-output buffers of cap entries each, then
+                                 // cap node accumulators
   uint64_t cap = 0;
   uint64_t len = 0;              // bytes appended since creation or reset
 };
 
 namespace {
 
-// level-2 nodes an append of n bytes can touch, plus room for the open ends
+// workspace entries for an append of n bytes: the level-2 nodes it can touch
+// (n / (128 W * 128) + 2) and two more
 uint64_t incr_nodes_for(const pmp_incr* h, uint64_t n) {
   const uint64_t C = (uint64_t)PMP_BLOCK * (h->wide ? 8 : 4);
-  return n / (C * PMP_BLOCK) + 2;
+  return n / (C * PMP_BLOCK) + 4;
+}
+
+size_t incr_workspace_bytes(uint64_t entries) {
+  return entries * (2 * sizeof(uint4) + sizeof(pmp::Slot));
 }
 
 int incr_grow(pmp_incr* h, uint64_t entries) {
@@ -743,12 +749,16 @@ int incr_grow(pmp_incr* h, uint64_t entries) {
     h->cap = 0;
     if (e != hipSuccess) return hip_fail(e, "hipFree");
   }
-  e = hipMalloc((void**)&h->z, 2 * entries * sizeof(uint4));
+  const size_t bytes = incr_workspace_bytes(entries);
+  e = hipMalloc((void**)&h->z, bytes);
   if (e != hipSuccess) {
     h->z = nullptr;
-    return fail(PMP_E_NOMEM, "incremental workspace of %llu bytes: %s",
-                (unsigned long long)(2 * entries * sizeof(uint4)), hipGetErrorString(e));
+    return fail(PMP_E_NOMEM, "incremental workspace of %llu bytes: %s", (unsigned long long)bytes,
+                hipGetErrorString(e));
   }
+  // the node accumulators start at zero and the kernels return them to zero
+  e = hipMemset(h->z, 0, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMemset");
   h->cap = entries;
   return PMP_OK;
 }
@@ -803,7 +813,7 @@ int pmp_incr_append(pmp_incr* h, const uint8_t* d_piece, uint64_t nbytes) {
   const uint64_t max_blocks = 1ull << 49;
   if (nbytes > (1ull << 62) || h->len + nbytes < h->len || (h->len + nbytes) / C + 1 > max_blocks)
     return fail(PMP_E_TOO_LONG, "the string would need more than %d levels", PMP_LEVELS);
-  if (nbytes / (C * PMP_BLOCK) + 2 > 0x7fffffffull)
+  if (nbytes / (C * pmp::INCR_SEG) + 2 > 0x7fffffffull)
     return fail(PMP_E_INVALID_ARG, "piece of %llu bytes: append it in smaller pieces", (unsigned long long)nbytes);
   const uint64_t len1 = h->len + nbytes;
   const uint64_t s1 = h->len / C, k = len1 / C - s1;
@@ -813,8 +823,9 @@ int pmp_incr_append(pmp_incr* h, const uint8_t* d_piece, uint64_t nbytes) {
     e = pmp::launch_incr_carry(h->st, t, d_piece, (int64_t)nbytes, h->stream);
     if (e != hipSuccess) return hip_fail(e, "carry launch");
   } else {
-    const uint64_t nwg = (s1 + k - 1) / PMP_BLOCK - s1 / PMP_BLOCK + 1;
-    int r = incr_grow(h, nwg + 2);
+    const uint64_t nwg = (s1 + k - 1) / pmp::INCR_SEG - s1 / pmp::INCR_SEG + 1;
+    const uint64_t nodes = (s1 + k - 1) / PMP_BLOCK - s1 / PMP_BLOCK + 1;
+    int r = incr_grow(h, nodes + 2);
     if (r != PMP_OK) return r;
     pmp::IncrArgs a{};
     a.piece = d_piece;
@@ -828,6 +839,7 @@ int pmp_incr_append(pmp_incr* h, const uint8_t* d_piece, uint64_t nbytes) {
     a.st = h->st;
     a.za = h->z;
     a.zb = h->z + h->cap;
+    a.slots = (pmp::Slot*)(h->z + 2 * h->cap);
     a.sums = h->sums;
     e = pmp::launch_incr_append(h->wide, a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "append launch");

@@ -7,17 +7,20 @@
 // open level-j node. Because Eq. (1) is a sum of products, the values need not
 // be kept: each is multiplied by its key as soon as it exists.
 //
-// An append that completes level-1 blocks is one launch. Workgroup w builds
-// level-2 node s1 / 128 + w out of the blocks of the piece that fall in it:
-// 32 groups of 8 lanes, a group per block at a time, each lane owning the
-// 16-byte pieces j, j + 8, ... of the block (its level-1 keys stay in
-// registers). A block is summed exactly over its 8 lanes, folded into a field
-// element (Sec. 6.2 and Algorithm 2) and multiplied by its level-2 key. A node
-// whose blocks all lie in the piece is finished by its workgroup. The last
-// workgroup to finish (a device-scope counter) completes the first and last
-// level-2 nodes with the state's open sums, stores the new open sums and
-// carried bytes, and climbs the levels above 2, which hold at most 1/128 of
-// the level-2 values.
+// An append that completes level-1 blocks is two launches. In the first,
+// workgroup w takes the w-th segment of 32 blocks (aligned to the string's
+// start) that the piece touches: 32 groups of 8 lanes, one block per group,
+// each lane loading the 16-byte pieces j, j + 8, ... of its block at once. A
+// block is summed exactly over its 8 lanes, folded into a field element
+// (Sec. 6.2 and Algorithm 2) and multiplied by its level-2 key; the
+// workgroup adds its 32 products and, when other segments share the node,
+// adds the reduced sum into the node's accumulator with relaxed atomics (no
+// fences: a device-scope release writes back the whole L2). The segment that
+// completes a node finishes it if all its blocks lie in the piece. The
+// second launch (one workgroup) completes the first and last level-2 nodes
+// with the state's open sums, stores the new open sums and carried bytes,
+// and climbs the levels above 2 (at most 1/128 of the level-2 values), one
+// wave per node.
 //
 // A digest pads the open block (end of Sec. 4), hashes it and climbs through
 // the open nodes to the root: the do-while of Algorithm 1 stops at the first
@@ -72,10 +75,10 @@ __device__ __forceinline__ Fe finish(typename Tr<WIDE>::Sum S, const typename Tr
   return reduce(S);
 }
 
-// One climb step inside a workgroup: the n_in new level-(j-1) values in[],
-// numbered s_in .. s_in + n_in - 1 within their level, go into the level-j
-// nodes; complete nodes are written to out[] in order, the open one (if any)
-// goes to part[j]. Returns the number of values written.
+// One climb step inside a workgroup, one wave per node: the n_in new
+// level-(j-1) values in[], numbered s_in .. s_in + n_in - 1 within their
+// level, go into the level-j nodes; complete nodes are written to out[] in
+// order, the open one (if any) goes to part[j]. Returns the number written.
 template <bool WIDE>
 __device__ uint64_t climb(IncrState* st, const typename Tr<WIDE>::key_t* keys, int j, const uint4* in,
                           uint64_t n_in, uint64_t s_in, uint4* out, uint64_t* pend) {
@@ -83,18 +86,22 @@ __device__ uint64_t climb(IncrState* st, const typename Tr<WIDE>::key_t* keys, i
   const uint64_t q0 = s_in / BLOCK, q1 = (s_in + n_in - 1) / BLOCK;
   const bool start_open = s_in % BLOCK != 0;
   const bool end_open = (s_in + n_in) % BLOCK != 0;
+  const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6);
   S old;
   from_words(old, st->part[j]);
   const typename Tr<WIDE>::key_t* a = keys + (j - 1) * BLOCK;
-  for (uint64_t q = q0 + threadIdx.x; q <= q1; q += blockDim.x) {
+  for (uint64_t q = q0 + wave; q <= q1; q += nw) {
     const uint64_t lo = q * BLOCK > s_in ? q * BLOCK : s_in;
     const uint64_t hi = q * BLOCK + BLOCK < s_in + n_in ? q * BLOCK + BLOCK : s_in + n_in;
     S acc;
     zero(acc);
-    for (uint64_t c = lo; c < hi; ++c) mac_fe(acc, a[c % BLOCK], unpack(in[c - s_in]));
-    if (q == q0 && start_open) add(acc, old);
-    if (hi == q * BLOCK + BLOCK) out[q - q0] = pack(finish<WIDE>(acc, keys, j));
-    else to_words(acc, pend);  // the last node, still open
+    for (uint64_t c = lo + lane; c < hi; c += 64) mac_fe(acc, a[c % BLOCK], unpack(in[c - s_in]));
+    reduce_lanes(acc, 1, 64);
+    if (lane == 0) {
+      if (q == q0 && start_open) add(acc, old);
+      if (hi == q * BLOCK + BLOCK) out[q - q0] = pack(finish<WIDE>(acc, keys, j));
+      else to_words(acc, pend);  // the last node, still open
+    }
   }
   __syncthreads();  // every reader of part[j] is done
   if (threadIdx.x == 0) {
@@ -111,8 +118,39 @@ __device__ uint64_t climb(IncrState* st, const typename Tr<WIDE>::key_t* keys, i
   return (s_in + n_in) / BLOCK - q0;
 }
 
+// Add field element v, with weight 1, into a node accumulator whose
+// segments in this launch number `target`; the call that brings the weight
+// to `target` gets the total (lo + 2^64 hi, at most four field elements) and
+// returns the accumulator to zero. Relaxed device-scope atomics only: the
+// completing call's own atomics come after every other contribution in each
+// word's order (the second atomic of a call is issued after the first has
+// returned), so no fence is needed.
 template <bool WIDE>
-__global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
+__device__ __forceinline__ bool add_to_node(Slot* sl, const Fe& v, uint32_t target, uint64_t* lo, uint32_t* hi) {
+  if constexpr (!WIDE) {
+    constexpr uint64_t M56 = (1ull << 56) - 1;
+    const uint64_t x = v.lo | ((uint64_t)v.hi << 32);
+    const uint64_t old = __hip_atomic_fetch_add(&sl->w0, (1ull << 56) + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(old >> 56) + 1 != target) return false;
+    __hip_atomic_store(&sl->w0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *lo = (old & M56) + x;
+    *hi = 0;
+    return true;
+  } else {
+    const uint64_t o0 = __hip_atomic_fetch_add(&sl->w0, v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t cy = o0 + v.lo < o0 ? 1u : 0u;
+    const uint64_t o1 =
+        __hip_atomic_fetch_add(&sl->w1, (1ull << 32) | (uint64_t)(v.hi + cy), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(o1 >> 32) + 1 != target) return false;
+    *lo = __hip_atomic_exchange(&sl->w0, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&sl->w1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *hi = (uint32_t)o1 + v.hi + cy;
+    return true;
+  }
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void incr_blocks(IncrArgs A) {
   using T = Tr<WIDE>;
   using S = typename T::Sum;
   using K = typename T::key_t;
@@ -120,45 +158,34 @@ __global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
   constexpr int C = BLOCK * W;        // bytes per level-1 block
   constexpr int NG = C / (16 * GL);   // 16-byte pieces per lane and block
   constexpr int KPG = 16 / W;         // words per 16-byte piece
+  constexpr int SPN = BLOCK / INCR_SEG;  // segments per level-2 node
+  static_assert(256 / GL == INCR_SEG, "one block per group of lanes");
   __shared__ uint32_t stg[C / 4];     // the block that begins in the carried bytes
-  __shared__ uint64_t red[256 / GL][3];
-  __shared__ uint64_t pend[3];
-  __shared__ uint32_t is_last;
+  __shared__ uint64_t red[INCR_SEG][3];
 
   const K* keys = (const K*)A.keys;
   const int tid = (int)threadIdx.x, g = tid / GL, j = tid % GL;
-  const uint64_t q = A.s1 / BLOCK + blockIdx.x;  // this workgroup's level-2 node
-  const uint64_t c_lo = q * BLOCK > A.s1 ? q * BLOCK : A.s1;
-  const uint64_t c_hi = q * BLOCK + BLOCK < A.s1 + A.k ? q * BLOCK + BLOCK : A.s1 + A.k;
+  const uint64_t sg0 = A.s1 / INCR_SEG, sg1 = (A.s1 + A.k - 1) / INCR_SEG;
+  const uint64_t sg = sg0 + blockIdx.x;  // this workgroup's segment
+  const uint64_t c = sg * INCR_SEG + g;  // this group's block
+  const bool act = c >= A.s1 && c < A.s1 + A.k;
+  const uint64_t i = c - A.s1;           // block index within the piece
+  const bool staged = blockIdx.x == 0 && A.t > 0;
 
-  if (blockIdx.x == 0 && A.t > 0) {  // carried bytes, then the piece's first bytes
+  if (staged) {  // carried bytes, then the piece's first bytes
     uint8_t* s8 = (uint8_t*)stg;
     const uint8_t* cb = (const uint8_t*)A.st->carry;
     for (int p = tid; p < C; p += 256) s8[p] = p < (int)A.t ? cb[p] : A.piece[p - (int)A.t];
     __syncthreads();
   }
 
-  // level-1 keys of this lane's pieces: word KPG (GL u + j) + v
-  K kk[NG * KPG];
-#pragma unroll
-  for (int u = 0; u < NG; ++u)
-#pragma unroll
-    for (int v = 0; v < KPG; ++v) kk[KPG * u + v] = keys[KPG * (GL * u + j) + v];
-  const uint64_t b1 = (uint64_t)keys[LMAX * BLOCK];
-  const K* a2 = keys + BLOCK;
-
-  // every block of the piece shares one byte misalignment
-  const uint64_t base = (uint64_t)(uintptr_t)A.piece - A.t;
+  // this lane's pieces of the block: all loads first
+  uint32_t d[NG][5];
+  const uint64_t base = (uint64_t)(uintptr_t)A.piece - A.t;  // every block shares its misalignment
   const uint32_t sh = (uint32_t)(base & 3u);
-
-  S node;
-  zero(node);
-  for (uint64_t c = q * BLOCK + g; c < c_hi; c += 256 / GL) {
-    if (c < c_lo) continue;
-    const uint64_t i = c - A.s1;  // block index within the piece
-    uint32_t d[NG][5];
-    uint32_t s_eff = sh;
-    if (i == 0 && A.t > 0) {
+  uint32_t s_eff = sh;
+  if (act) {
+    if (staged && i == 0) {
 #pragma unroll
       for (int u = 0; u < NG; ++u) {
         const uint32_t* p = stg + 4 * (GL * u + j);
@@ -180,6 +207,17 @@ __global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
         d[u][4] = sh ? *(const uint32_t*)__builtin_assume_aligned(p + 16, 4) : 0u;
       }
     }
+  }
+  // level-1 keys of this lane's pieces: word KPG (GL u + j) + v
+  K kk[NG * KPG];
+#pragma unroll
+  for (int u = 0; u < NG; ++u)
+#pragma unroll
+    for (int v = 0; v < KPG; ++v) kk[KPG * u + v] = keys[KPG * (GL * u + j) + v];
+
+  S node;
+  zero(node);
+  if (act) {
     S s;
     if constexpr (WIDE) {
       P64 p;
@@ -201,40 +239,59 @@ __global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
         for (int v = 0; v < 4; ++v) mac_vv(s.lo, s.hi, kk[4 * u + v], align_bytes(d[u][v + 1], d[u][v], s_eff));
     }
     group_sum<GL>(s);  // the block's exact sum, in every lane of the group
-    add_word(s, b1);
-    mac_fe(node, a2[c % BLOCK], reduce(s));
+    add_word(s, (uint64_t)keys[LMAX * BLOCK]);
+    mac_fe(node, keys[BLOCK + c % BLOCK], reduce(s));
   }
   if (j == 0) to_words(node, red[g]);
   __syncthreads();
+  if (tid != 0) return;
 
-  if (tid == 0) {
-    S tot;
-    zero(tot);
-    for (int h = 0; h < 256 / GL; ++h) {
-      S x;
-      from_words(x, red[h]);
-      add(tot, x);
-    }
-    if (c_lo == q * BLOCK && c_hi == q * BLOCK + BLOCK) {
-      A.za[blockIdx.x] = pack(finish<WIDE>(tot, keys, 2));  // a whole node
-    } else {
-      to_words(tot, A.sums + 4 * (blockIdx.x == 0 ? 0 : 1));  // first or last node, open
-    }
-    __threadfence();  // release this workgroup's results
-    const uint32_t prev = atomicAdd(&A.st->done, 1u);
-    is_last = prev == A.nwg - 1 ? 1u : 0u;
+  S tot;
+  zero(tot);
+  for (int h = 0; h < INCR_SEG; ++h) {
+    S x;
+    from_words(x, red[h]);
+    add(tot, x);
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();  // acquire the other workgroups' results
+  // the segments of this node that the piece touches
+  const uint64_t q = sg / SPN, q0 = A.s1 / BLOCK, slot = q - q0;
+  const uint64_t f = sg0 > q * SPN ? sg0 : q * SPN, l = sg1 < q * SPN + SPN - 1 ? sg1 : q * SPN + SPN - 1;
+  const uint32_t nseg = (uint32_t)(l - f + 1);
+  if (nseg > 1) {
+    // this segment's share of the node, reduced (a sum of at most 32
+    // products, well inside the fold's range)
+    uint64_t lo;
+    uint32_t hi;
+    if (!add_to_node<WIDE>(A.slots + slot, reduce(tot), nseg, &lo, &hi)) return;
+    zero(tot);
+    if constexpr (WIDE) {
+      tot.w0 = lo;
+      tot.w1 = hi;
+    } else {
+      tot.lo = lo;
+    }
+  }
+  const uint64_t c_lo = q * BLOCK > A.s1 ? q * BLOCK : A.s1;
+  const uint64_t c_hi = q * BLOCK + BLOCK < A.s1 + A.k ? q * BLOCK + BLOCK : A.s1 + A.k;
+  if (c_lo == q * BLOCK && c_hi == q * BLOCK + BLOCK) A.za[slot] = pack(finish<WIDE>(tot, keys, 2));
+  else to_words(tot, A.sums + 4 * (slot == 0 ? 0 : 1));  // first or last node, open
+}
 
-  // level 2: the nodes that this piece shares with the string before or
-  // after it
+// Second launch of an append, one workgroup: the level-2 nodes that the
+// piece shares with the string before or after it, the carried bytes, then
+// the levels above 2.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void incr_tree(IncrArgs A) {
+  using S = typename Tr<WIDE>::Sum;
+  using K = typename Tr<WIDE>::key_t;
+  __shared__ uint64_t pend[3];
+  const K* keys = (const K*)A.keys;
+  const int tid = (int)threadIdx.x;
   if (tid == 0) {
     IncrState* st = A.st;
     const bool start_open = A.s1 % BLOCK != 0;
     const bool end_open = (A.s1 + A.k) % BLOCK != 0;
-    const bool one = A.nwg == 1;
+    const bool one = A.s1 / BLOCK == (A.s1 + A.k - 1) / BLOCK;
     uint64_t np[3] = {0, 0, 0};
     if (start_open || (one && end_open)) {
       S x;
@@ -255,9 +312,8 @@ __global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
     st->part[2][0] = np[0];
     st->part[2][1] = np[1];
     st->part[2][2] = np[2];
-    st->done = 0;  // ready for the next append
   }
-  // the bytes carried to the next piece (block 0's reader has finished)
+  // the bytes carried to the next piece
   {
     uint8_t* cb = (uint8_t*)A.st->carry;
     const uint8_t* src = A.piece + (A.n - (int64_t)A.r_new);
@@ -265,7 +321,6 @@ __global__ __launch_bounds__(256) void incr_append(IncrArgs A) {
   }
   __syncthreads();
 
-  // levels 3 and up
   uint64_t n_in = (A.s1 + A.k) / BLOCK - A.s1 / BLOCK;  // complete level-2 nodes
   uint64_t s_in = A.s1 / BLOCK;                         // level-2 values before this piece
   uint4* in = A.za;
@@ -338,8 +393,13 @@ __global__ void incr_reset(IncrState* st) {
 }  // namespace
 
 hipError_t launch_incr_append(int wide, const IncrArgs& a, hipStream_t s) {
-  if (wide) hipLaunchKernelGGL(incr_append<true>, dim3(a.nwg), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(incr_append<false>, dim3(a.nwg), dim3(256), 0, s, a);
+  if (wide) {
+    hipLaunchKernelGGL(incr_blocks<true>, dim3(a.nwg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(incr_tree<true>, dim3(1), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(incr_blocks<false>, dim3(a.nwg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(incr_tree<false>, dim3(1), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -62,19 +62,18 @@ struct KArgs {
 //     values z already produced for the open level-j node (b_j not added);
 //     3 words (PM+32: lo, hi, 0; PM+64: w0, w1, w2), the fourth unused.
 //   carry: the bytes of the open level-1 block (fewer than 128 W).
-//   done: workgroups of the running append that have finished (0 between
-//     launches).
 struct IncrState {
   uint64_t part[9][4];
-  uint32_t done;
-  uint32_t pad_[3];
   uint32_t carry[(1024 + 16) / 4];
 };
 
 // One append that completes at least one level-1 block. The piece's bytes
 // follow the t carried bytes; blocks s1 .. s1 + k - 1 (numbered from the
 // string's start) are completed by it; r_new bytes are carried afterwards.
-// Workgroup w builds level-2 node s1 / 128 + w.
+// Workgroup w of the first launch takes segment s1 / 32 + w (32 blocks, a
+// quarter of a level-2 node). Per level-2 node touched (numbered from node
+// s1 / 128): an accumulator Slot for its segments (0 between launches).
+constexpr int INCR_SEG = 32;
 struct IncrArgs {
   const uint8_t* piece;
   int64_t n;
@@ -86,9 +85,10 @@ struct IncrArgs {
   uint32_t pad_;
   const void* keys;
   IncrState* st;
-  uint4* za;       // level outputs, ping-pong: each nwg + 2 entries
+  uint4* za;        // level outputs, ping-pong: each `cap` entries
   uint4* zb;
-  uint64_t* sums;  // raw sums of the first and last level-2 nodes (2 x 4 words)
+  Slot* slots;      // per node touched
+  uint64_t* sums;   // sums of the first and last level-2 nodes, when open (2 x 4 words)
 };
 
 // host side (pmp_api.cpp)
