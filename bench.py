@@ -46,11 +46,11 @@ DESCR = {
 }
 
 
-def kernel_source_hash() -> str:
-    """sha256 (first 16 hex digits) of the batch kernel's sources with their
-    comments and blank lines removed: edits to comments keep it."""
+def kernel_source_hash(main: str = "pmp_kernels.hip") -> str:
+    """sha256 (first 16 hex digits) of a kernel file and the device headers
+    with their comments and blank lines removed: edits to comments keep it."""
     h = hashlib.sha256()
-    for f in ("pmp_kernels.hip", "pmp_device.hpp", "pmp_internal.h"):
+    for f in (main, "pmp_device.hpp", "pmp_internal.h"):
         with open(os.path.join(ROOT, "paper_1609_09840_amd", "csrc", f), encoding="utf-8") as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         for line in text.splitlines():
@@ -60,15 +60,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(config: str):
+def read_traffic(config: str, kernel: str = KERNEL, main: str = "pmp_kernels.hip"):
     """HBM bytes per launch from profiles/<kernel>_<config>_counters.json if it
     was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{config}_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash(main):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -260,9 +260,12 @@ def plain_gpu(keep, dev, max_strings: int = 4000):
 
 
 def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20), reps: int = 3) -> dict:
-    """One string of `total` bytes appended in equal pieces, then a digest;
-    HIP events on the object's stream around `reps` whole passes (reset,
-    appends, digest). The digest must equal pmp_hash32/64 of the string."""
+    """One string of `total` bytes appended in equal pieces, then a digest.
+    HIP events on the object's stream: one pair around the appends of a pass
+    (per-append time = its share; an append is two launches), one more after
+    the digest; `reps` passes after a warm one, each after a reset. The digest
+    must equal pmp_hash32/64 of the string. `roofline`: the largest pieces'
+    append rate against the HBM peak (algorithmic bytes = the piece)."""
     import torch
 
     from paper_1609_09840_amd import pmp
@@ -280,26 +283,37 @@ def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20)
         h = pmp.Incr(wide, keys)
         h.reserve(max(pieces))
         for piece in pieces:
-            def one_pass():
+            n_app = -(-total // piece)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            t_app = t_all = 0.0
+            for r in range(reps + 1):
                 h.reset()
+                ev[0].record()
                 for o in range(0, total, piece):
                     h.append(data[o:o + piece])
-                return h.digest()
-            d = one_pass()  # warm
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                d = one_pass()
-            e1.record()
-            e1.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            if not torch.equal(d, ref):
-                raise RuntimeError("incremental digest disagrees with the batched path")
-            gbs = total / (ms * 1e-3) / 1e9
-            res["runs"].append({"variant": "PM+64" if wide else "PM+32", "piece_bytes": piece,
-                                "appends": -(-total // piece), "ms": round(ms, 4), "value": round(gbs, 1),
-                                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+                ev[1].record()
+                d = h.digest()
+                ev[2].record()
+                ev[2].synchronize()
+                if r:  # the first pass warms up
+                    t_app += ev[0].elapsed_time(ev[1]) / reps
+                    t_all += ev[0].elapsed_time(ev[2]) / reps
+                if not torch.equal(d, ref):
+                    raise RuntimeError("incremental digest disagrees with the batched path")
+            res["runs"].append({"variant": "PM+64" if wide else "PM+32", "piece_bytes": piece, "appends": n_app,
+                                "append_us": round(t_app * 1e3 / n_app, 2),
+                                "append_GBps": round(total / (t_app * 1e-3) / 1e9, 1),
+                                "digest_us": round((t_all - t_app) * 1e3, 2),
+                                "value": round(total / (t_all * 1e-3) / 1e9, 1)})
         h.close()
+    big = [r for r in res["runs"] if r["piece_bytes"] == max(pieces)]
+    best = max(big, key=lambda r: r["append_GBps"])
+    res["roofline"] = {"bound": "hbm", "kernel": "incr_blocks + incr_tree (one append)",
+                       "variant": best["variant"], "piece_bytes": best["piece_bytes"],
+                       "achieved": best["append_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(best["append_GBps"] / HBM_PEAK_GBS, 4),
+                       "traffic": read_traffic("256mib_" + ("pm64" if best["variant"] == "PM+64" else "pm32"),
+                                               "incr_blocks", "pmp_incr.hip")}
     return res
 
 
