@@ -709,6 +709,54 @@ int pmp_probe_mad_rate(double* mads_per_s) {
 }
 
 // ---------------------------------------------------------------------------
+// Hash table of variable-length keys: the batch kernel hashes, the table
+// kernels bucket and probe.
+uint64_t pmp_table_work_bytes(uint64_t nbuckets) { return pmp::table_work_bytes(nbuckets); }
+
+int pmp_table_build(pmp_plan* plan, const pmp_batch* keys, uint64_t nbuckets, int64_t* d_bucket_start,
+                    int64_t* d_entries, void* d_work, uint64_t work_bytes, pmp_stream_t stream) {
+  if (!keys || !d_bucket_start || !d_work || (keys->count > 0 && !d_entries))
+    return fail(PMP_E_INVALID_ARG, "NULL argument");
+  int r = check_batch(keys);
+  if (r) return r;
+  if (keys->flags & PMP_OUT_FIELD) return fail(PMP_E_INVALID_ARG, "a table keys on n-bit outputs (no PMP_OUT_FIELD)");
+  if (nbuckets < 1 || nbuckets > (1ull << 31)) return fail(PMP_E_INVALID_ARG, "nbuckets must be in [1, 2^31]");
+  if (work_bytes < pmp::table_work_bytes(nbuckets))
+    return fail(PMP_E_INVALID_ARG, "d_work holds %llu bytes, %llu needed", (unsigned long long)work_bytes,
+                (unsigned long long)pmp::table_work_bytes(nbuckets));
+  if (keys->count > 0) {
+    r = run_two(plan, keys, nullptr, (hipStream_t)stream);
+    if (r) return r;
+  }
+  hipError_t e = pmp::launch_table_build(keys->out, keys->wide, keys->count, nbuckets, d_bucket_start, d_entries,
+                                         d_work, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "table build launch");
+  return PMP_OK;
+}
+
+int pmp_table_probe(pmp_plan* plan, const pmp_batch* queries, const pmp_batch* keys, uint64_t nbuckets,
+                    const int64_t* d_bucket_start, const int64_t* d_entries, int64_t* d_result, pmp_stream_t stream) {
+  if (!queries || !keys || !d_bucket_start || (queries->count > 0 && !d_result))
+    return fail(PMP_E_INVALID_ARG, "NULL argument");
+  int r = check_batch(queries);
+  if (r) return r;
+  r = check_batch(keys);
+  if (r) return r;
+  if (queries->wide != keys->wide || queries->keys != keys->keys || queries->flags != keys->flags)
+    return fail(PMP_E_INVALID_ARG, "queries and keys must share the variant, the key table and the flags");
+  if (keys->flags & PMP_OUT_FIELD) return fail(PMP_E_INVALID_ARG, "a table keys on n-bit outputs (no PMP_OUT_FIELD)");
+  if (nbuckets < 1 || nbuckets > (1ull << 31)) return fail(PMP_E_INVALID_ARG, "nbuckets must be in [1, 2^31]");
+  if (queries->count == 0) return PMP_OK;
+  r = run_two(plan, queries, nullptr, (hipStream_t)stream);
+  if (r) return r;
+  hipError_t e = pmp::launch_table_probe(queries->buf, queries->offsets, queries->count, queries->out, keys->buf,
+                                         keys->offsets, keys->out, keys->wide, nbuckets, d_bucket_start, d_entries,
+                                         d_result, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "table probe launch");
+  return PMP_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Incremental hashing: the host keeps the byte count, from which every count
 // the kernels need follows (blocks completed, nodes per level, carried bytes).
 }  // extern "C"

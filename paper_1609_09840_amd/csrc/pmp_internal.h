@@ -108,6 +108,12 @@ hipError_t launch_incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, in
 hipError_t launch_incr_digest(int wide, const IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
                               void* out, uint32_t flags, hipStream_t s);
 hipError_t launch_incr_reset(IncrState* st, hipStream_t s);
+uint64_t table_work_bytes(uint64_t m);
+hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, int64_t* start, int64_t* entries,
+                              void* work, hipStream_t s);
+hipError_t launch_table_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
+                              const int64_t* koff, const void* kh, uint32_t wide, uint64_t m, const int64_t* start,
+                              const int64_t* entries, int64_t* result, hipStream_t s);
 hipError_t launch_debug_fold(int wide, const void* w0, const void* w1, const uint32_t* w2, void* z, int64_t n,
                              hipStream_t s);
 

@@ -1,0 +1,187 @@
+// Hash table of variable-length keys on PM+ outputs (the use that motivates
+// the paper, Sec. 1 and Sec. 3: the bucket of key i is h_i mod M, which keeps
+// the family almost universal and regular by Lemma 1 and Lemma 8).
+//
+// Build (after the keys are hashed by the batch kernel): count the keys of
+// each bucket with atomics, an exclusive scan of the counts gives the CSR
+// bucket starts, and a scatter with per-bucket atomic cursors places each key
+// index in its bucket. The order inside a bucket is whatever the atomics
+// give; the probe does not depend on it.
+//
+// Probe (after the queries are hashed): one lane per query walks its bucket,
+// skips keys whose full n-bit hash or length differs, compares the bytes of
+// the rest and keeps the smallest equal key index (or -1).
+#include "pmp_device.hpp"
+#include "pmp_internal.h"
+
+namespace pmp {
+
+namespace {
+
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = 256 * SCAN_ITEMS;  // counts per scan workgroup
+
+__device__ __forceinline__ uint64_t hash_at(const void* h, uint32_t wide, int64_t i) {
+  return wide ? ((const uint64_t*)h)[i] : (uint64_t)((const uint32_t*)h)[i];
+}
+
+__global__ void tab_zero(uint32_t* a, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+
+__global__ void tab_count(const void* h, uint32_t wide, int64_t n, uint64_t m, uint32_t* cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(cnt + hash_at(h, wide, i) % m, 1u);
+}
+
+// exclusive scan of the 256 thread values of a workgroup; *total gets the sum
+__device__ uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
+  __shared__ uint64_t ws[4];
+  const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+  uint64_t x = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    if (lane >= d) x += ((uint64_t)hi << 32) | lo;
+  }
+  if (lane == 63) ws[wave] = x;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) before += ws[w];
+    all += ws[w];
+  }
+  __syncthreads();  // ws may be reused by the next call
+  *total = all;
+  return before + x - v;
+}
+
+// Phase 1: each workgroup scans SCAN_TILE counts into start[] (relative to
+// its tile) and leaves the tile's total in bsum[].
+__global__ void tab_scan_tiles(const uint32_t* cnt, uint64_t m, int64_t* start, uint64_t* bsum) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint64_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < m ? cnt[base + k] : 0u;
+    s += v[k];
+  }
+  uint64_t total;
+  uint64_t run = block_excl_scan(s, &total);
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < m) start[base + k] = (int64_t)run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Phase 2 (one workgroup): exclusive scan of the tile totals, in place;
+// start[m] = the number of keys.
+__global__ void tab_scan_totals(uint64_t* bsum, uint64_t nb, int64_t* start, uint64_t m) {
+  uint64_t carry = 0;
+  for (uint64_t b0 = 0; b0 < nb; b0 += 256) {
+    const uint64_t i = b0 + threadIdx.x;
+    const uint64_t v = i < nb ? bsum[i] : 0;
+    uint64_t total;
+    const uint64_t x = block_excl_scan(v, &total);
+    if (i < nb) bsum[i] = carry + x;
+    carry += total;
+  }
+  if (threadIdx.x == 0) start[m] = (int64_t)carry;
+}
+
+// Phase 3: add each tile's offset.
+__global__ void tab_scan_add(int64_t* start, uint64_t m, const uint64_t* bsum) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  const int64_t add = (int64_t)bsum[blockIdx.x];
+  for (int k = threadIdx.x; k < SCAN_TILE; k += 256)
+    if (base + k < m) start[base + k] += add;
+}
+
+__global__ void tab_scatter(const void* h, uint32_t wide, int64_t n, uint64_t m, const int64_t* start, uint32_t* fill,
+                            int64_t* entries) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = hash_at(h, wide, i) % m;
+    entries[start[b] + atomicAdd(fill + b, 1u)] = i;
+  }
+}
+
+// up to 4 bytes of a string at p, little-endian, of which `rem` (>= 1) are
+// wanted: aligned dword loads, each holding at least one wanted byte
+__device__ __forceinline__ uint32_t load_upto4(const uint8_t* p, int64_t rem) {
+  const uint64_t a = (uint64_t)(uintptr_t)p;
+  const uint32_t sh = (uint32_t)(a & 3u);
+  const uint32_t* w = (const uint32_t*)(uintptr_t)(a - sh);
+  const uint32_t take = rem < 4 ? (uint32_t)rem : 4u;
+  const uint32_t lo = w[0];
+  const uint32_t hi = sh + take > 4 ? w[1] : 0u;
+  uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, sh);
+  if (take < 4) x &= (1u << (8 * take)) - 1u;
+  return x;
+}
+
+__device__ bool bytes_equal(const uint8_t* a, const uint8_t* b, int64_t len) {
+  for (int64_t o = 0; o < len; o += 4)
+    if (load_upto4(a + o, len - o) != load_upto4(b + o, len - o)) return false;
+  return true;
+}
+
+__global__ void tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
+                          const int64_t* koff, const void* kh, uint32_t wide, uint64_t m, const int64_t* start,
+                          const int64_t* entries, int64_t* result) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q0 = qoff[q], len = qoff[q + 1] - q0;
+    const uint64_t hq = hash_at(qh, wide, q);
+    const uint64_t b = hq % m;
+    int64_t best = -1;
+    for (int64_t e = start[b], e1 = start[b + 1]; e < e1; ++e) {
+      const int64_t i = entries[e];
+      if ((best >= 0 && i > best) || hash_at(kh, wide, i) != hq) continue;
+      const int64_t k0 = koff[i];
+      if (koff[i + 1] - k0 != len) continue;
+      if (bytes_equal(qbuf + q0, kbuf + k0, len)) best = i;
+    }
+    result[q] = best;
+  }
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+}  // namespace
+
+uint64_t table_work_bytes(uint64_t m) {
+  const uint64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
+  return ((4 * m + 7) & ~7ull) + 8 * (nb + 1);
+}
+
+hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, int64_t* start, int64_t* entries,
+                              void* work, hipStream_t s) {
+  uint32_t* cnt = (uint32_t*)work;
+  uint64_t* bsum = (uint64_t*)((char*)work + ((4 * m + 7) & ~7ull));
+  const uint64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
+  if (n > 0) hipLaunchKernelGGL(tab_count, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, cnt);
+  hipLaunchKernelGGL(tab_scan_tiles, dim3((unsigned)nb), dim3(256), 0, s, cnt, m, start, bsum);
+  hipLaunchKernelGGL(tab_scan_totals, dim3(1), dim3(256), 0, s, bsum, nb, start, m);
+  hipLaunchKernelGGL(tab_scan_add, dim3((unsigned)nb), dim3(256), 0, s, start, m, bsum);
+  if (n > 0) {
+    hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
+    hipLaunchKernelGGL(tab_scatter, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, start, cnt, entries);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_table_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
+                              const int64_t* koff, const void* kh, uint32_t wide, uint64_t m, const int64_t* start,
+                              const int64_t* entries, int64_t* result, hipStream_t s) {
+  if (nq > 0)
+    hipLaunchKernelGGL(tab_probe, dim3(grid_for(nq)), dim3(256), 0, s, qbuf, qoff, nq, qh, kbuf, koff, kh, wide, m,
+                       start, entries, result);
+  return hipGetLastError();
+}
+
+}  // namespace pmp

@@ -140,6 +140,8 @@ def _load():
         "pmp_server_status": [vp],
         "pmp_hash_plain": [i32, vp, u64, vp, i64, vp, vp, u32, vp, u64, vp],
         "pmp_debug_fold": [i32, vp, vp, vp, vp, i64, vp],
+        "pmp_table_build": [vp, ctypes.POINTER(pmp_batch), u64, vp, vp, vp, u64, vp],
+        "pmp_table_probe": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), u64, vp, vp, vp, vp],
         "pmp_incr_create": [i32, vp, vp, ctypes.POINTER(vp)],
         "pmp_incr_reserve": [vp, u64],
         "pmp_incr_append": [vp, vp, u64],
@@ -152,6 +154,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.pmp_table_work_bytes.argtypes = [u64]
+    lib.pmp_table_work_bytes.restype = u64
     lib.pmp_last_error.restype = ctypes.c_char_p
     lib.pmp_version.restype = ctypes.c_char_p
     return lib
@@ -425,6 +429,53 @@ class Incr:
             self.close()
         except Exception:
             pass
+
+
+class Table:
+    """Hash table over the strings of one batch (pmp_table_*): bucket =
+    hash mod nbuckets, CSR arrays on the device. The key batch (and its
+    tensors) is kept: probes read its bytes and hashes."""
+
+    def __init__(self, wide: bool, buf, offsets, keys, nbuckets: int, flags: int = 0, stream=None,
+                 plan: Plan | None = None):
+        import torch
+
+        if flags & PMP_OUT_FIELD:
+            raise ValueError("a table keys on n-bit outputs (no PMP_OUT_FIELD)")
+        count = offsets.numel() - 1
+        dev = offsets.device
+        self.wide, self.flags, self.nbuckets, self.plan = bool(wide), flags, int(nbuckets), plan
+        self.tensors = (buf, offsets, keys)
+        self.hashes = _out_for(wide, count, flags, dev)
+        self.batch = make_batch(wide, buf, offsets, keys, self.hashes, flags)
+        self.bucket_start = torch.empty(self.nbuckets + 1, dtype=torch.int64, device=dev)
+        self.entries = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+        nw = int(_lib.pmp_table_work_bytes(self.nbuckets))
+        self.work = torch.empty(max(nw, 8), dtype=torch.uint8, device=dev)
+        _check(_lib.pmp_table_build(_plan_ptr(plan), ctypes.byref(self.batch), self.nbuckets,
+                                    _dev_ptr(self.bucket_start, "bucket_start"), _dev_ptr(self.entries, "entries"),
+                                    _dev_ptr(self.work, "work"), nw, _stream(stream)))
+
+    def probe(self, qbuf, qoffsets, out=None, qhashes=None, stream=None):
+        """Smallest key index equal to each query's bytes, or -1 (int64)."""
+        import torch
+
+        n = qoffsets.numel() - 1
+        dev = qoffsets.device
+        if qhashes is None:
+            qhashes = _out_for(self.wide, n, self.flags, dev)
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        qb = make_batch(self.wide, qbuf, qoffsets, self.tensors[2], qhashes, self.flags)
+        _check(_lib.pmp_table_probe(_plan_ptr(self.plan), ctypes.byref(qb), ctypes.byref(self.batch), self.nbuckets,
+                                    _dev_ptr(self.bucket_start, "bucket_start"), _dev_ptr(self.entries, "entries"),
+                                    _dev_ptr(out, "out"), _stream(stream)))
+        return out[:n]
+
+
+def pmp_table_build(wide: bool, buf, offsets, keys, nbuckets: int, flags: int = 0, stream=None,
+                    plan: Plan | None = None) -> Table:
+    return Table(wide, buf, offsets, keys, nbuckets, flags, stream, plan)
 
 
 def pmp_incr_create(wide: bool, keys, stream=None) -> Incr:
