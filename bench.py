@@ -17,7 +17,10 @@ Prints ONE JSON line. Besides the headline value it carries:
   plain_gpu     the one-string-per-launch GPU form on a prefix of the batch;
   incremental   one 1 GiB string hashed through pmp_incr_* in pieces of
                 1 MiB, 16 MiB and 256 MiB (both variants), checked equal to
-                the batched path's hash of the same string.
+                the batched path's hash of the same string;
+  hash_table    pmp_table_build over C2-shaped keys and pmp_table_probe of as
+                many queries (half present), with the hashing and table
+                kernels timed apart.
 """
 from __future__ import annotations
 
@@ -317,6 +320,82 @@ def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20)
     return res
 
 
+def gather_strings(buf: np.ndarray, offsets: np.ndarray, idx: np.ndarray):
+    """The strings idx of a ragged set, back to back (vectorized)."""
+    lens = offsets[idx + 1] - offsets[idx]
+    off = np.zeros(len(idx) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    pos = np.repeat(offsets[idx] - off[:-1], lens) + np.arange(off[-1], dtype=np.int64)
+    return buf[pos], off
+
+
+def hash_table(dev, nkeys: int = 1 << 20, nbuckets: int = 1 << 20, reps: int = 5) -> dict:
+    """Build a table over C2-shaped keys (PM+32, lengths uniform in [8, 256])
+    and probe as many queries: even-numbered ones copy a random key, odd ones
+    are fresh strings. HIP events: whole build and probe calls, and the
+    hashing launches alone (pmp_hash32 on the same batches), over `reps`
+    calls after a warm one. Every hit is checked to carry the query's hash
+    and length, and the hit count to be the number of copied queries."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+    from paper_1609_09840_amd import workloads as W
+
+    rng = np.random.default_rng(606)
+    keys_rg = W.from_lengths(rng.integers(8, 257, nkeys), 607, False)
+    fresh = W.from_lengths(rng.integers(8, 257, nkeys), 608, False)
+    # query q copies a random key when q is even, else it is fresh string q: one
+    # gather from the keys and fresh strings laid end to end
+    pool = np.concatenate([keys_rg.buf, fresh.buf])
+    pool_off = np.concatenate([keys_rg.offsets[:-1], fresh.offsets + keys_rg.offsets[-1]])
+    take_copy = np.arange(nkeys) % 2 == 0
+    idx = np.where(take_copy, rng.integers(0, nkeys, nkeys), nkeys + np.arange(nkeys))
+    qbuf, qoff = gather_strings(pool, pool_off, idx)
+    lens = np.diff(qoff)
+    kn = pmp.pmp_expand_keys32(1)
+    keys = torch.from_numpy(kn.view(np.int32)).to(dev).view(torch.uint32)
+    dk = torch.from_numpy(keys_rg.buf).to(dev)
+    dko = torch.from_numpy(keys_rg.offsets).to(dev)
+    dq = torch.from_numpy(qbuf).to(dev)
+    dqo = torch.from_numpy(qoff).to(dev)
+    plan = pmp.Plan(0)
+    plan.reserve(max(dk.numel(), dq.numel()), nkeys)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        ev[0].record()
+        for _ in range(reps):
+            r = fn()
+        ev[1].record()
+        ev[1].synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps, r
+
+    t = pmp.Table(False, dk, dko, keys, nbuckets, plan=plan)
+    qh = torch.empty(nkeys, dtype=torch.uint32, device=dev)
+    res = torch.empty(nkeys, dtype=torch.int64, device=dev)
+    build_ms, _ = timed(lambda: pmp.Table(False, dk, dko, keys, nbuckets, plan=plan))
+    probe_ms, _ = timed(lambda: t.probe(dq, dqo, out=res, qhashes=qh))
+    hk_ms, _ = timed(lambda: pmp.pmp_hash32(dk, dko, keys, out=t.hashes, plan=plan))
+    hq_ms, _ = timed(lambda: pmp.pmp_hash32(dq, dqo, keys, out=qh, plan=plan))
+    torch.cuda.synchronize()
+    got = res.cpu().numpy()
+    kh = t.hashes.cpu().numpy()
+    qhn = qh.cpu().numpy()
+    hit = got >= 0
+    if hit.sum() != take_copy.sum() or not np.array_equal(kh[got[hit]], qhn[hit]) or \
+            not np.array_equal(np.diff(keys_rg.offsets)[got[hit]], lens[hit]):
+        raise RuntimeError("hash-table probe results fail their checks")
+    kb, qb = int(keys_rg.offsets[-1]), int(qoff[-1])
+    return {"keys": nkeys, "buckets": nbuckets, "key_bytes": kb, "queries": nkeys, "query_bytes": qb,
+            "hits": int(hit.sum()),
+            "build_ms": round(build_ms, 4), "build_Mkeys_per_s": round(nkeys / build_ms / 1e3, 1),
+            "build_GBps": round(kb / (build_ms * 1e-3) / 1e9, 1), "build_hash_ms": round(hk_ms, 4),
+            "probe_ms": round(probe_ms, 4), "probe_Mqueries_per_s": round(nkeys / probe_ms / 1e3, 1),
+            "probe_GBps": round(qb / (probe_ms * 1e-3) / 1e9, 1), "probe_hash_ms": round(hq_ms, 4),
+            "note": "GB/s = key or query payload bytes per second of the whole call (hashing + table kernels)"}
+
+
 def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505, per_launch: int = 16,
                   sat_passes: int = 8):
     """Serving workload: Poisson arrivals of requests of 1..4096 strings with
@@ -391,6 +470,8 @@ def main():
     ap.add_argument("--no-incr", action="store_true", help="skip the incremental (one string in pieces) pass")
     ap.add_argument("--incr-only", action="store_true",
                     help="only run the incremental pass and print its JSON (for profiling its kernels)")
+    ap.add_argument("--no-table", action="store_true", help="skip the hash-table pass")
+    ap.add_argument("--table-only", action="store_true", help="only run the hash-table pass and print its JSON")
     ap.add_argument("--incr-pieces", default="1048576,16777216,268435456",
                     help="piece sizes of the incremental pass, in bytes, comma-separated")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -417,6 +498,9 @@ def main():
         print(json.dumps({"copy_bytes": args.calibrate_copy, "launches": 5}), flush=True)
         return
     incr_pieces = tuple(int(x) for x in args.incr_pieces.split(",") if x)
+    if args.table_only:
+        print(json.dumps({"hash_table": hash_table(dev)}), flush=True)
+        return
     if args.incr_only:
         print(json.dumps({"incremental": incremental(dev, pieces=incr_pieces)}), flush=True)
         return
@@ -511,6 +595,8 @@ def main():
         rec["serving"] = serving_sweep(dev)
     if not args.no_incr:
         rec["incremental"] = incremental(dev, pieces=incr_pieces)
+    if not args.no_table:
+        rec["hash_table"] = hash_table(dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

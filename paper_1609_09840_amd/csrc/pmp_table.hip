@@ -107,23 +107,51 @@ __global__ void tab_scatter(const void* h, uint32_t wide, int64_t n, uint64_t m,
   }
 }
 
-// up to 4 bytes of a string at p, little-endian, of which `rem` (>= 1) are
-// wanted: aligned dword loads, each holding at least one wanted byte
-__device__ __forceinline__ uint32_t load_upto4(const uint8_t* p, int64_t rem) {
-  const uint64_t a = (uint64_t)(uintptr_t)p;
-  const uint32_t sh = (uint32_t)(a & 3u);
-  const uint32_t* w = (const uint32_t*)(uintptr_t)(a - sh);
-  const uint32_t take = rem < 4 ? (uint32_t)rem : 4u;
-  const uint32_t lo = w[0];
-  const uint32_t hi = sh + take > 4 ? w[1] : 0u;
-  uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, sh);
-  if (take < 4) x &= (1u << (8 * take)) - 1u;
-  return x;
+__device__ __forceinline__ const uint32_t* gdw(uint64_t a) {
+  return (const uint32_t*)(const __attribute__((address_space(1))) uint32_t*)(uintptr_t)a;
 }
 
+// Bytes [o, o + take) of a string at p (take <= 16) as four little-endian
+// dwords, zero past `take`: the aligned dwords holding them are loaded (each
+// holds at least one wanted byte) and realigned.
+__device__ __forceinline__ void load16_of(const uint8_t* p, int64_t o, uint32_t take, uint32_t* x) {
+  const uint64_t a = (uint64_t)(uintptr_t)p + (uint64_t)o;
+  const uint32_t sh = (uint32_t)(a & 3u);
+  const uint32_t* w = gdw(a - sh);
+  uint32_t d[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) d[k] = 4u * k < sh + take ? w[k] : 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t v = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
+    const int32_t left = (int32_t)take - 4 * k;  // wanted bytes in this dword
+    if (left <= 0) v = 0;
+    else if (left < 4) v &= (1u << (8 * left)) - 1u;
+    x[k] = v;
+  }
+}
+
+// 32 bytes per step, both strings' loads issued before the comparison
 __device__ bool bytes_equal(const uint8_t* a, const uint8_t* b, int64_t len) {
-  for (int64_t o = 0; o < len; o += 4)
-    if (load_upto4(a + o, len - o) != load_upto4(b + o, len - o)) return false;
+  for (int64_t o = 0; o < len; o += 32) {
+    const int64_t r = len - o;
+    const uint32_t t0 = r < 16 ? (uint32_t)r : 16u;
+    const uint32_t t1 = r <= 16 ? 0u : (r < 32 ? (uint32_t)(r - 16) : 16u);
+    uint32_t xa[8], xb[8];
+    load16_of(a, o, t0, xa);
+    load16_of(b, o, t0, xb);
+    if (t1) {
+      load16_of(a, o + 16, t1, xa + 4);
+      load16_of(b, o + 16, t1, xb + 4);
+    } else {
+#pragma unroll
+      for (int k = 4; k < 8; ++k) xa[k] = xb[k] = 0;
+    }
+    uint32_t diff = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) diff |= xa[k] ^ xb[k];
+    if (diff) return false;
+  }
   return true;
 }
 
