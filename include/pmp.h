@@ -279,6 +279,36 @@ int pmp_server_replay(pmp_server* server, const pmp_request* reqs, int64_t n, co
 int pmp_server_status(pmp_server* server);
 
 /* ---------------------------------------------------------------------- */
+/* PM+128: the same construction over p = 2^128 + 51, the smallest prime
+ * above 2^128 (Table "smallestprimes"), with 16-byte words. The paper gives
+ * only the prime for n = 128; the rest follows PM+32 / PM+64: words after
+ * the 0x01 byte and zero padding to a multiple of 16 (end of Sec. 4),
+ * Eq. (1) with 128-bit keys, the tree of Algorithm 1 (leaves on level-1
+ * keys, at least one and at most 8 levels), output h mod 2^128 (Sec. 5).
+ * Keys a in [1, 2^128 - 50] (p - kappa - 1 with kappa = 2 (k - 1) = 100,
+ * extended from Table "parameters"), b in [0, 2^128). Sec. 7 defines no
+ * mixer for n = 128: the output is never mixed and PMP_NO_MIX changes
+ * nothing.
+ *
+ * Key table: PMP_KEYS entries of two uint64 (lo, hi), a[8][128] then b[8]
+ * (2064 uint64). pmp_expand_keys128 fills a HOST table from splitmix64(seed),
+ * two draws per entry (low half first), redrawing an `a` outside its range;
+ * pmp_check_keys128 returns PMP_E_KEY_RANGE for an `a` above 2^128 - 50.
+ *
+ * pmp_hash128: string i = d_buf[d_offsets[i] .. d_offsets[i+1]) (device
+ * memory, as pmp_hash32). d_out: count x 2 uint64 (lo, hi of h mod 2^128),
+ * or with PMP_OUT_FIELD count x 3 uint64 (lo, hi, top bit of h < p). A pair
+ * of offsets out of order or past buf_bytes is hashed as an empty string.
+ * d_scratch: device memory of pmp_hash128_scratch_bytes(count, buf_bytes)
+ * bytes at least. Four launches on `stream`, asynchronous; no allocation. */
+int pmp_expand_keys128(uint64_t seed, uint64_t* keys_out);
+int pmp_check_keys128(const uint64_t* keys);
+uint64_t pmp_hash128_scratch_bytes(int64_t count, uint64_t buf_bytes);
+int pmp_hash128(const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets, int64_t count,
+                const uint64_t* d_keys, void* d_out, uint32_t flags, void* d_scratch, uint64_t scratch_bytes,
+                pmp_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
 /* Hash table of variable-length keys (Sec. 1 and Sec. 3: a randomly chosen
  * hash function picks each key's bucket; bucket = h mod M keeps the family
  * almost universal (Lemma 1) and regular (Lemma 8)). h is the n-bit output

@@ -709,6 +709,55 @@ int pmp_probe_mad_rate(double* mads_per_s) {
 }
 
 // ---------------------------------------------------------------------------
+// PM+128 over p = 2^128 + 51.
+int pmp_expand_keys128(uint64_t seed, uint64_t* keys_out) {
+  if (!keys_out) return fail(PMP_E_INVALID_ARG, "keys_out is NULL");
+  uint64_t st = seed;
+  for (int i = 0; i < PMP_KEYS; ++i) {
+    for (;;) {
+      const uint64_t lo = splitmix64(&st), hi = splitmix64(&st);
+      keys_out[2 * i] = lo;
+      keys_out[2 * i + 1] = hi;
+      if (i >= PMP_LEVELS * PMP_BLOCK) break;  // b: any 128-bit value
+      // a in [1, 2^128 - 50]
+      if ((lo | hi) != 0 && !(hi == ~0ull && lo > ~0ull - 49)) break;
+    }
+  }
+  return PMP_OK;
+}
+
+int pmp_check_keys128(const uint64_t* keys) {
+  if (!keys) return fail(PMP_E_INVALID_ARG, "keys is NULL");
+  for (int i = 0; i < PMP_LEVELS * PMP_BLOCK; ++i) {
+    const uint64_t lo = keys[2 * i], hi = keys[2 * i + 1];
+    if (hi == ~0ull && lo > ~0ull - 49) return fail(PMP_E_KEY_RANGE, "key %d above 2^128 - 50", i);
+  }
+  return PMP_OK;
+}
+
+uint64_t pmp_hash128_scratch_bytes(int64_t count, uint64_t buf_bytes) {
+  return count < 0 ? 0 : pmp::pm128_scratch_bytes(count, buf_bytes);
+}
+
+int pmp_hash128(const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offsets, int64_t count,
+                const uint64_t* d_keys, void* d_out, uint32_t flags, void* d_scratch, uint64_t scratch_bytes,
+                pmp_stream_t stream) {
+  if (count < 0 || count > ((int64_t)1 << 40)) return fail(PMP_E_INVALID_ARG, "bad count");
+  if (count == 0) return PMP_OK;
+  if (!d_offsets || !d_keys || !d_out || !d_scratch || (!d_buf && buf_bytes))
+    return fail(PMP_E_INVALID_ARG, "NULL argument");
+  if (flags & ~(PMP_NO_MIX | PMP_OUT_FIELD)) return fail(PMP_E_INVALID_ARG, "unknown flag bits");
+  if (buf_bytes / 16 >= (1ull << 56) - 1) return fail(PMP_E_TOO_LONG, "buffer too long for 8 levels");
+  if (scratch_bytes < pmp::pm128_scratch_bytes(count, buf_bytes))
+    return fail(PMP_E_INVALID_ARG, "d_scratch holds %llu bytes, %llu needed", (unsigned long long)scratch_bytes,
+                (unsigned long long)pmp::pm128_scratch_bytes(count, buf_bytes));
+  hipError_t e = pmp::launch_pm128(d_buf, buf_bytes, d_offsets, count, d_keys, d_out, flags, d_scratch,
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "PM+128 launch");
+  return PMP_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Hash table of variable-length keys: the batch kernel hashes, the table
 // kernels bucket and probe.
 uint64_t pmp_table_work_bytes(uint64_t nbuckets) { return pmp::table_work_bytes(nbuckets); }

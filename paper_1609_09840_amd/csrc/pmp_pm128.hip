@@ -1,0 +1,349 @@
+// PM+128: the PM+ construction over p = 2^128 + 51 (the smallest prime above
+// 2^128, Table "smallestprimes") with 128-bit words, for batches of ragged
+// strings. The paper gives only the prime for n = 128; words, Eq. (1), the
+// tree of Algorithm 1 and the output h mod 2^128 (Sec. 5) follow the PM+32 /
+// PM+64 construction, with keys a in [1, 2^128 - 50] (kappa = 2 (k - 1) =
+// 100) and no Sec. 7 mixer.
+//
+// Arithmetic: a 128 x 128 product is four 64 x 64 -> 128 products; a block
+// sum (at most 128 products plus b, below 2^264) is kept exactly in five
+// 64-bit limbs and reduced once per block with 2^128 = -51 (mod p):
+//   S = s0 + 2^128 s1 + 2^256 s2 == s0 + 51 (2^128 - s1) + 2601 (1 + s2)
+// (adding 51 p keeps every term non-negative), which is below 53 * 2^128;
+// one more step v0 - 51 v1 (plus p when negative) lands in [0, p).
+//
+// Launches: (1) the number of level-2 nodes of each string (1 for a string of
+// one block) and an exclusive scan of those counts; (2) one wave per (string,
+// level-2 node): lane l forms words 2l and 2l + 1 of each of the node's
+// blocks, the block's exact sum is reduced over the wave and folded, and the
+// node sums a_{2,i} z_i; a string of one block or one node is finished here;
+// (3) one wave per longer string climbs its level-2 values (levels 3 and up)
+// in place.
+#include "pmp_device.hpp"
+#include "pmp_internal.h"
+
+namespace pmp {
+
+namespace {
+
+constexpr uint64_t K128 = 51;
+constexpr int W16 = 16;                      // bytes per word
+constexpr uint64_t BLK_BYTES = BLOCK * W16;  // 2 KiB per level-1 block
+
+struct A5 {
+  uint64_t w[5];
+};
+struct F128 {  // a field element lo + 2^64 hi + 2^128 top, below p
+  uint64_t lo, hi;
+  uint32_t top;
+};
+
+__device__ __forceinline__ void zero(A5& s) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) s.w[i] = 0;
+}
+
+// s += v * 2^(64 k), k <= 2
+__device__ __forceinline__ void add_at(A5& s, u128 v, int k) {
+  u128 t = (u128)s.w[k] + (uint64_t)v;
+  s.w[k] = (uint64_t)t;
+  t = (u128)s.w[k + 1] + (uint64_t)(v >> 64) + (uint64_t)(t >> 64);
+  s.w[k + 1] = (uint64_t)t;
+  uint64_t c = (uint64_t)(t >> 64);
+  for (int i = k + 2; i < 5; ++i) {
+    t = (u128)s.w[i] + c;
+    s.w[i] = (uint64_t)t;
+    c = (uint64_t)(t >> 64);
+  }
+}
+
+__device__ __forceinline__ void add(A5& s, const A5& t) {
+  uint64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const u128 x = (u128)s.w[i] + t.w[i] + c;
+    s.w[i] = (uint64_t)x;
+    c = (uint64_t)(x >> 64);
+  }
+}
+
+// s += a * x, a and x 128-bit
+__device__ __forceinline__ void mac(A5& s, uint64_t a0, uint64_t a1, uint64_t x0, uint64_t x1) {
+  add_at(s, (u128)a0 * x0, 0);
+  add_at(s, (u128)a0 * x1, 1);
+  add_at(s, (u128)a1 * x0, 1);
+  add_at(s, (u128)a1 * x1, 2);
+}
+
+// s += a * z, z a field element
+__device__ __forceinline__ void mac_fe(A5& s, uint64_t a0, uint64_t a1, const F128& z) {
+  mac(s, a0, a1, z.lo, z.hi);
+  if (z.top) add_at(s, (u128)a0 | ((u128)a1 << 64), 2);
+}
+
+// S mod p for S below 2^264 (see the header)
+__device__ F128 fold(const A5& S) {
+  const u128 s0 = (u128)S.w[0] | ((u128)S.w[1] << 64);
+  const u128 s1 = (u128)S.w[2] | ((u128)S.w[3] << 64);
+  const uint64_t s2 = S.w[4];
+  // V = s0 + 51 (2^128 - s1) + 2601 (1 + s2) as v0 + 2^128 v1
+  A5 V;
+  zero(V);
+  add_at(V, s0, 0);
+  if (s1 == 0) {
+    V.w[2] += K128;
+  } else {
+    const u128 m1 = (u128)0 - s1;  // 2^128 - s1
+    add_at(V, (u128)(uint64_t)m1 * K128, 0);
+    add_at(V, (u128)(uint64_t)(m1 >> 64) * K128, 1);
+  }
+  add_at(V, (u128)(K128 * K128) * (1 + s2), 0);
+  const u128 v0 = (u128)V.w[0] | ((u128)V.w[1] << 64);
+  const uint64_t v1 = V.w[2];  // at most 52
+  F128 z;
+  if (v0 >= (u128)(K128 * v1)) {
+    const u128 r = v0 - K128 * v1;
+    z.lo = (uint64_t)r;
+    z.hi = (uint64_t)(r >> 64);
+    z.top = 0;
+  } else {
+    // v0 < 51 v1 is small: r = v0 - 51 v1 + p = 2^128 + d
+    const int64_t d = (int64_t)(uint64_t)v0 + (int64_t)K128 - (int64_t)(K128 * v1);
+    if (d >= 0) {
+      z.lo = (uint64_t)d;
+      z.hi = 0;
+      z.top = 1;
+    } else {
+      const u128 r = (u128)0 - (u128)(uint64_t)(-d);
+      z.lo = (uint64_t)r;
+      z.hi = (uint64_t)(r >> 64);
+      z.top = 0;
+    }
+  }
+  return z;
+}
+
+__device__ __forceinline__ uint64_t shx64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ void wave_sum(A5& s) {
+  for (int m = 1; m < 64; m <<= 1) {
+    A5 t;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) t.w[i] = shx64(s.w[i], m);
+    add(s, t);
+  }
+}
+
+// key i of level j (1-based) and b_j: entries of two uint64 (lo, hi)
+__device__ __forceinline__ void key_a(const uint64_t* keys, int j, uint32_t i, uint64_t* a0, uint64_t* a1) {
+  const uint64_t* k = keys + 2 * ((uint64_t)(j - 1) * BLOCK + i);
+  *a0 = k[0];
+  *a1 = k[1];
+}
+__device__ __forceinline__ void add_b(A5& s, const uint64_t* keys, int j) {
+  const uint64_t* k = keys + 2 * (LMAX * BLOCK + (j - 1));
+  add_at(s, (u128)k[0] | ((u128)k[1] << 64), 0);
+}
+
+// word w of a string (start s, len bytes), padded (end of Sec. 4), as two
+// 64-bit halves; reads stay inside [lo, hi)
+__device__ __forceinline__ void word128(const uint8_t* s, int64_t len, int64_t w, const uint8_t* lo, const uint8_t* hi,
+                                        uint64_t* x0, uint64_t* x1) {
+  const int64_t r = len - W16 * w;
+  uint32_t x[4] = {0, 0, 0, 0};
+  if (r >= 0) {
+    const uint8_t* p = s + W16 * w;
+    const uint32_t sh = (uint32_t)((uintptr_t)p & 3u);
+    const uint8_t* a4 = p - sh;
+    const Q q = load16_guarded(a4, lo, hi);
+    const uint32_t d4 = sh ? load4_guarded(a4 + 16, lo, hi) : 0u;
+    const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], d4};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = tail_word32(align_bytes(d[u + 1], d[u], sh), r - 4 * u);
+  }
+  *x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+  *x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+}
+
+__device__ __forceinline__ int64_t blocks_of(int64_t len) { return (len / W16 + 1 + BLOCK - 1) / BLOCK; }
+__device__ __forceinline__ int64_t units_of(int64_t len) {
+  const int64_t n1 = blocks_of(len);
+  return n1 == 1 ? 1 : (n1 + BLOCK - 1) / BLOCK;
+}
+
+__device__ __forceinline__ int64_t str_len(const int64_t* off, int64_t i, uint64_t buf_bytes) {
+  const int64_t o0 = off[i], o1 = off[i + 1];
+  // offsets out of order or past the buffer: the string is taken as empty
+  return (o0 < 0 || o1 < o0 || (uint64_t)o1 > buf_bytes) ? 0 : o1 - o0;
+}
+
+__device__ __forceinline__ void store128(void* out, uint32_t flags, int64_t i, const F128& z) {
+  uint64_t* o = (uint64_t*)out;
+  if (flags & PMP_OUT_FIELD) {
+    o[3 * i] = z.lo;
+    o[3 * i + 1] = z.hi;
+    o[3 * i + 2] = z.top;
+  } else {  // h mod 2^128
+    o[2 * i] = z.lo;
+    o[2 * i + 1] = z.hi;
+  }
+}
+
+__global__ void p128_count(const int64_t* off, int64_t count, uint64_t buf_bytes, uint32_t* cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    cnt[i] = (uint32_t)units_of(str_len(off, i, buf_bytes));
+}
+
+struct P128Args {
+  const uint8_t* buf;
+  uint64_t buf_bytes;
+  const int64_t* off;
+  int64_t count;
+  const uint64_t* keys;
+  void* out;
+  uint32_t flags;
+  const int64_t* start;  // count + 1: first unit of each string
+  F128* z2;              // level-2 values of strings with more than one node, at start[s] + k
+  uint64_t zcap;         // entries of z2 (only offsets that decrease can ask for more)
+};
+
+// One wave per unit (string, level-2 node), found by a 64-ary search of start.
+__global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int64_t units = A.start[A.count];
+  if (g >= units) return;
+  // the string s with start[s] <= g < start[s + 1]
+  int64_t lo = 0, hi = A.count;
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t idx = lo + (int64_t)lane * step;
+    const bool le = idx < hi && A.start[idx] <= g;
+    const uint64_t mask = __ballot(le);
+    const int last = 63 - __clzll((long long)mask);
+    lo = lo + (int64_t)last * step;
+    hi = lo + step < hi ? lo + step : hi;
+  }
+  const int64_t s = lo;
+  const int64_t k = g - A.start[s];
+  const int64_t len = str_len(A.off, s, A.buf_bytes);
+  const uint8_t* str = A.buf + (len ? A.off[s] : 0);
+  const uint8_t* blo = A.buf;
+  const uint8_t* bhi = A.buf + A.buf_bytes;
+  const int64_t n1 = blocks_of(len);
+
+  uint64_t ka[4];  // level-1 keys of words 2 lane, 2 lane + 1
+  key_a(A.keys, 1, 2 * lane, &ka[0], &ka[1]);
+  key_a(A.keys, 1, 2 * lane + 1, &ka[2], &ka[3]);
+
+  A5 node;
+  zero(node);
+  const int64_t c0 = n1 == 1 ? 0 : k * BLOCK;
+  const int64_t c1 = n1 == 1 ? 1 : (c0 + BLOCK < n1 ? c0 + BLOCK : n1);
+  F128 z1 = {0, 0, 0};
+  for (int64_t c = c0; c < c1; ++c) {
+    A5 sum;
+    zero(sum);
+    uint64_t x0, x1;
+    word128(str, len, c * BLOCK + 2 * lane, blo, bhi, &x0, &x1);
+    mac(sum, ka[0], ka[1], x0, x1);
+    word128(str, len, c * BLOCK + 2 * lane + 1, blo, bhi, &x0, &x1);
+    mac(sum, ka[2], ka[3], x0, x1);
+    wave_sum(sum);
+    add_b(sum, A.keys, 1);
+    z1 = fold(sum);
+    uint64_t a0, a1;
+    key_a(A.keys, 2, (uint32_t)(c % BLOCK), &a0, &a1);
+    mac_fe(node, a0, a1, z1);
+  }
+  if (lane != 0) return;
+  if (n1 == 1) {  // one block: the root is level 1
+    store128(A.out, A.flags, s, z1);
+    return;
+  }
+  add_b(node, A.keys, 2);
+  const F128 z2 = fold(node);
+  if (n1 <= BLOCK) store128(A.out, A.flags, s, z2);  // one node: the root is level 2
+  else if ((uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = z2;
+}
+
+// One wave per string with more than one level-2 node: levels 3 and up, each
+// level's values written over the previous ones (node q's value goes to
+// index q, below its first input 128 q once q > 0, and node 0 is read before
+// it is written).
+__global__ __launch_bounds__(256) void p128_upper(P128Args A) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  if (s >= A.count) return;
+  const int64_t len = str_len(A.off, s, A.buf_bytes);
+  const int64_t n1 = blocks_of(len);
+  if (n1 <= BLOCK) return;
+  int64_t n = (n1 + BLOCK - 1) / BLOCK;  // level-2 values
+  if ((uint64_t)(A.start[s] + n) > A.zcap) return;
+  F128* v = A.z2 + A.start[s];
+  for (int j = 3; n > 1 && j <= LMAX; ++j) {
+    const int64_t nout = (n + BLOCK - 1) / BLOCK;
+    for (int64_t q = 0; q < nout; ++q) {
+      A5 sum;
+      zero(sum);
+      for (int u = 0; u < 2; ++u) {
+        const int64_t i = q * BLOCK + 2 * lane + u;
+        if (i < n) {
+          uint64_t a0, a1;
+          key_a(A.keys, j, (uint32_t)(i % BLOCK), &a0, &a1);
+          mac_fe(sum, a0, a1, v[i]);
+        }
+      }
+      wave_sum(sum);
+      if (lane == 0) {
+        add_b(sum, A.keys, j);
+        v[q] = fold(sum);
+      }
+      __threadfence();  // node q's value is visible before any lane reads it
+    }
+    n = nout;
+  }
+  if (lane == 0) store128(A.out, A.flags, s, v[0]);
+}
+
+unsigned grid_for(int64_t threads) {
+  const int64_t g = (threads + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// scratch: counts (4 per string, rounded to 8), unit starts (8 per string
+// and one), the scan's tile totals, then 32 bytes per possible unit
+uint64_t pm128_scratch_bytes(int64_t count, uint64_t buf_bytes) {
+  const uint64_t n = (uint64_t)count;
+  const uint64_t units = 2 * n + buf_bytes / (BLK_BYTES * BLOCK) + 2;
+  return ((4 * n + 7) & ~7ull) + 8 * (n + 1) + excl_scan_work_bytes(n) + sizeof(F128) * units;
+}
+
+hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* offsets, int64_t count,
+                        const uint64_t* keys, void* out, uint32_t flags, void* scratch, hipStream_t st) {
+  const uint64_t n = (uint64_t)count;
+  char* p = (char*)scratch;
+  uint32_t* cnt = (uint32_t*)p;
+  p += (4 * n + 7) & ~7ull;
+  int64_t* start = (int64_t*)p;
+  p += 8 * (n + 1);
+  uint64_t* bsum = (uint64_t*)p;
+  p += excl_scan_work_bytes(n);
+  F128* z2 = (F128*)p;
+  const uint64_t units_bound = 2 * n + buf_bytes / (BLK_BYTES * BLOCK) + 2;
+  hipLaunchKernelGGL(p128_count, dim3(grid_for(count) > 65536 ? 65536 : grid_for(count)), dim3(256), 0, st, offsets,
+                     count, buf_bytes, cnt);
+  hipError_t e = launch_excl_scan_u32(cnt, n, start, bsum, st);
+  if (e != hipSuccess) return e;
+  P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, start, z2, units_bound};
+  hipLaunchKernelGGL(p128_nodes, dim3(grid_for((int64_t)units_bound * 64)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(p128_upper, dim3(grid_for(count * 64)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace pmp

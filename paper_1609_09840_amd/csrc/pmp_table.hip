@@ -186,16 +186,24 @@ uint64_t table_work_bytes(uint64_t m) {
   return ((4 * m + 7) & ~7ull) + 8 * (nb + 1);
 }
 
+uint64_t excl_scan_work_bytes(uint64_t m) { return 8 * ((m + SCAN_TILE - 1) / SCAN_TILE + 1); }
+
+hipError_t launch_excl_scan_u32(const uint32_t* cnt, uint64_t m, int64_t* start, uint64_t* bsum, hipStream_t s) {
+  const uint64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb) hipLaunchKernelGGL(tab_scan_tiles, dim3((unsigned)nb), dim3(256), 0, s, cnt, m, start, bsum);
+  hipLaunchKernelGGL(tab_scan_totals, dim3(1), dim3(256), 0, s, bsum, nb, start, m);
+  if (nb) hipLaunchKernelGGL(tab_scan_add, dim3((unsigned)nb), dim3(256), 0, s, start, m, bsum);
+  return hipGetLastError();
+}
+
 hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, int64_t* start, int64_t* entries,
                               void* work, hipStream_t s) {
   uint32_t* cnt = (uint32_t*)work;
   uint64_t* bsum = (uint64_t*)((char*)work + ((4 * m + 7) & ~7ull));
-  const uint64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
   if (n > 0) hipLaunchKernelGGL(tab_count, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, cnt);
-  hipLaunchKernelGGL(tab_scan_tiles, dim3((unsigned)nb), dim3(256), 0, s, cnt, m, start, bsum);
-  hipLaunchKernelGGL(tab_scan_totals, dim3(1), dim3(256), 0, s, bsum, nb, start, m);
-  hipLaunchKernelGGL(tab_scan_add, dim3((unsigned)nb), dim3(256), 0, s, start, m, bsum);
+  hipError_t e = launch_excl_scan_u32(cnt, m, start, bsum, s);
+  if (e != hipSuccess) return e;
   if (n > 0) {
     hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
     hipLaunchKernelGGL(tab_scatter, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, start, cnt, entries);

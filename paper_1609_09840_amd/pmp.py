@@ -140,6 +140,9 @@ def _load():
         "pmp_server_status": [vp],
         "pmp_hash_plain": [i32, vp, u64, vp, i64, vp, vp, u32, vp, u64, vp],
         "pmp_debug_fold": [i32, vp, vp, vp, vp, i64, vp],
+        "pmp_expand_keys128": [u64, vp],
+        "pmp_check_keys128": [vp],
+        "pmp_hash128": [vp, u64, vp, i64, vp, vp, u32, vp, u64, vp],
         "pmp_table_build": [vp, ctypes.POINTER(pmp_batch), u64, vp, vp, vp, u64, vp],
         "pmp_table_probe": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), u64, vp, vp, vp, vp],
         "pmp_incr_create": [i32, vp, vp, ctypes.POINTER(vp)],
@@ -154,6 +157,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.pmp_hash128_scratch_bytes.argtypes = [i64, u64]
+    lib.pmp_hash128_scratch_bytes.restype = u64
     lib.pmp_table_work_bytes.argtypes = [u64]
     lib.pmp_table_work_bytes.restype = u64
     lib.pmp_last_error.restype = ctypes.c_char_p
@@ -208,6 +213,18 @@ def pmp_expand_keys64(seed: int) -> np.ndarray:
     k = np.zeros(PMP_KEYS, dtype=np.uint64)
     _check(_lib.pmp_expand_keys64(seed, k.ctypes.data_as(ctypes.c_void_p)))
     return k
+
+
+def pmp_expand_keys128(seed: int) -> np.ndarray:
+    """PM+128 key table: 2064 uint64, entries (lo, hi), a[8][128] then b[8]."""
+    k = np.zeros(2 * PMP_KEYS, dtype=np.uint64)
+    _check(_lib.pmp_expand_keys128(seed, k.ctypes.data_as(ctypes.c_void_p)))
+    return k
+
+
+def pmp_check_keys128(keys: np.ndarray) -> int:
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    return _lib.pmp_check_keys128(k.ctypes.data_as(ctypes.c_void_p))
 
 
 def pmp_check_keys32(keys: np.ndarray) -> int:
@@ -304,6 +321,30 @@ def pmp_hash64(buf, offsets, keys, out=None, flags: int = 0, stream=None, plan: 
                buf_bytes: int | None = None):
     """PM+64 counterpart of pmp_hash32 (uint64[1032] keys)."""
     return _hash(True, buf, offsets, keys, out, flags, stream, plan, buf_bytes)
+
+
+def pmp_hash128(buf, offsets, keys, out=None, flags: int = 0, scratch=None, stream=None,
+                buf_bytes: int | None = None):
+    """PM+128 of string i = buf[offsets[i]:offsets[i+1]] (device tensors:
+    uint8 buf, int64 offsets, uint64[2064] keys). out: count x 2 uint64
+    (h mod 2^128, low half first) or, with PMP_OUT_FIELD, count x 3."""
+    import torch
+
+    count = offsets.numel() - 1
+    if buf_bytes is None:
+        buf_bytes = buf.numel()
+    if keys.dtype != torch.uint64 or keys.numel() != 2 * PMP_KEYS:
+        raise ValueError("keys must be a device tensor of 2064 uint64")
+    if out is None:
+        out = torch.empty(count * (3 if flags & PMP_OUT_FIELD else 2), dtype=torch.uint64, device=offsets.device)
+    need = int(_lib.pmp_hash128_scratch_bytes(count, buf_bytes))
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(max(need, 8), dtype=torch.uint8, device=offsets.device)
+    bp = _dev_ptr(buf, "buf") if buf.numel() else ctypes.c_void_p(0)
+    _check(_lib.pmp_hash128(bp, buf_bytes, _dev_ptr(offsets, "offsets"), count, _dev_ptr(keys, "keys"),
+                            _dev_ptr(out, "out"), flags, _dev_ptr(scratch, "scratch"), scratch.numel(),
+                            _stream(stream)))
+    return out
 
 
 def make_batch(wide: bool, buf, offsets, keys, out, flags: int = 0, buf_bytes: int | None = None) -> pmp_batch:
