@@ -20,7 +20,9 @@ Prints ONE JSON line. Besides the headline value it carries:
                 the batched path's hash of the same string;
   hash_table    pmp_table_build over C2-shaped keys and pmp_table_probe of as
                 many queries (half present), with the hashing and table
-                kernels timed apart.
+                kernels timed apart;
+  pm128         PM+128 (p = 2^128 + 51) on the C3 shape (64 x 16 MiB) and
+                the C2 shape (2^20 strings of 8-256 B).
 """
 from __future__ import annotations
 
@@ -396,6 +398,45 @@ def hash_table(dev, nkeys: int = 1 << 20, nbuckets: int = 1 << 20, reps: int = 5
             "note": "GB/s = key or query payload bytes per second of the whole call (hashing + table kernels)"}
 
 
+def pm128(dev, reps: int = 5) -> dict:
+    """pmp_hash128 on two shapes with device-resident seeded bytes; HIP events
+    around `reps` back-to-back calls after a warm one (a call is seven
+    launches: counts, a three-launch scan, short strings, nodes, upper
+    levels)."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    kt = torch.from_numpy(pmp.pmp_expand_keys128(1).view(np.int64)).to(dev).view(torch.uint64)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1280)
+    rng = np.random.default_rng(1281)
+    shapes = {"c3-shaped: 64 x 16 MiB": np.full(64, 16 << 20, np.int64),
+              "c2-shaped: 2^20 strings, lengths uniform in [8, 256] B": rng.integers(8, 257, 1 << 20)}
+    runs = []
+    for name, lens in shapes.items():
+        off = np.zeros(len(lens) + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        buf = torch.randint(0, 256, (int(off[-1]),), dtype=torch.uint8, device=dev, generator=g)
+        doff = torch.from_numpy(off).to(dev)
+        out = torch.empty(2 * len(lens), dtype=torch.uint64, device=dev)
+        scratch = torch.empty(int(pmp._lib.pmp_hash128_scratch_bytes(len(lens), buf.numel())), dtype=torch.uint8,
+                              device=dev)
+        pmp.pmp_hash128(buf, doff, kt, out=out, scratch=scratch)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pmp.pmp_hash128(buf, doff, kt, out=out, scratch=scratch)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = int(off[-1]) / (ms * 1e-3) / 1e9
+        runs.append({"workload": name, "payload_bytes": int(off[-1]), "ms": round(ms, 4), "value": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        del buf, scratch
+    return {"unit": "GB/s", "runs": runs}
+
+
 def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505, per_launch: int = 16,
                   sat_passes: int = 8):
     """Serving workload: Poisson arrivals of requests of 1..4096 strings with
@@ -471,6 +512,8 @@ def main():
     ap.add_argument("--incr-only", action="store_true",
                     help="only run the incremental pass and print its JSON (for profiling its kernels)")
     ap.add_argument("--no-table", action="store_true", help="skip the hash-table pass")
+    ap.add_argument("--no-pm128", action="store_true", help="skip the PM+128 pass")
+    ap.add_argument("--pm128-only", action="store_true", help="only run the PM+128 pass and print its JSON")
     ap.add_argument("--table-only", action="store_true", help="only run the hash-table pass and print its JSON")
     ap.add_argument("--incr-pieces", default="1048576,16777216,268435456",
                     help="piece sizes of the incremental pass, in bytes, comma-separated")
@@ -498,6 +541,9 @@ def main():
         print(json.dumps({"copy_bytes": args.calibrate_copy, "launches": 5}), flush=True)
         return
     incr_pieces = tuple(int(x) for x in args.incr_pieces.split(",") if x)
+    if args.pm128_only:
+        print(json.dumps({"pm128": pm128(dev)}), flush=True)
+        return
     if args.table_only:
         print(json.dumps({"hash_table": hash_table(dev)}), flush=True)
         return
@@ -597,6 +643,8 @@ def main():
         rec["incremental"] = incremental(dev, pieces=incr_pieces)
     if not args.no_table:
         rec["hash_table"] = hash_table(dev)
+    if not args.no_pm128:
+        rec["pm128"] = pm128(dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

@@ -300,7 +300,9 @@ int pmp_server_status(pmp_server* server);
  * or with PMP_OUT_FIELD count x 3 uint64 (lo, hi, top bit of h < p). A pair
  * of offsets out of order or past buf_bytes is hashed as an empty string.
  * d_scratch: device memory of pmp_hash128_scratch_bytes(count, buf_bytes)
- * bytes at least. Four launches on `stream`, asynchronous; no allocation. */
+ * bytes at least. Seven launches on `stream` (string counts, a three-launch
+ * scan, short strings, level-2 nodes, upper levels), asynchronous; no
+ * allocation. */
 int pmp_expand_keys128(uint64_t seed, uint64_t* keys_out);
 int pmp_check_keys128(const uint64_t* keys);
 uint64_t pmp_hash128_scratch_bytes(int64_t count, uint64_t buf_bytes);

@@ -12,13 +12,13 @@
 // (adding 51 p keeps every term non-negative), which is below 53 * 2^128;
 // one more step v0 - 51 v1 (plus p when negative) lands in [0, p).
 //
-// Launches: (1) the number of level-2 nodes of each string (1 for a string of
-// one block) and an exclusive scan of those counts; (2) one wave per (string,
-// level-2 node): lane l forms words 2l and 2l + 1 of each of the node's
-// blocks, the block's exact sum is reduced over the wave and folded, and the
-// node sums a_{2,i} z_i; a string of one block or one node is finished here;
-// (3) one wave per longer string climbs its level-2 values (levels 3 and up)
-// in place.
+// Launches: (1) the number of level-2 nodes of each string of more than one
+// block and an exclusive scan of those counts; (2) strings of one block,
+// eight lanes each; (3) one wave per (string, level-2 node): lane l forms
+// words 2l and 2l + 1 of each of the node's blocks, the block's exact sum is
+// reduced over the wave and folded, and the node sums a_{2,i} z_i; a string
+// of one node is finished here; (4) one wave per longer string climbs its
+// level-2 values (levels 3 and up) in place.
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
 
@@ -123,6 +123,10 @@ __device__ F128 fold(const A5& S) {
   return z;
 }
 
+__device__ __forceinline__ const uint8_t* gp16(uint64_t a) {
+  return (const uint8_t*)(const __attribute__((address_space(1))) uint8_t*)(uintptr_t)a;
+}
+
 __device__ __forceinline__ uint64_t shx64(uint64_t v, int m) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
   const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
@@ -169,9 +173,11 @@ __device__ __forceinline__ void word128(const uint8_t* s, int64_t len, int64_t w
 }
 
 __device__ __forceinline__ int64_t blocks_of(int64_t len) { return (len / W16 + 1 + BLOCK - 1) / BLOCK; }
+// units of the node kernel: level-2 nodes; strings of one block have none
+// (the short-string kernel takes them)
 __device__ __forceinline__ int64_t units_of(int64_t len) {
   const int64_t n1 = blocks_of(len);
-  return n1 == 1 ? 1 : (n1 + BLOCK - 1) / BLOCK;
+  return n1 == 1 ? 0 : (n1 + BLOCK - 1) / BLOCK;
 }
 
 __device__ __forceinline__ int64_t str_len(const int64_t* off, int64_t i, uint64_t buf_bytes) {
@@ -239,35 +245,98 @@ __global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
   key_a(A.keys, 1, 2 * lane, &ka[0], &ka[1]);
   key_a(A.keys, 1, 2 * lane + 1, &ka[2], &ka[3]);
 
+  // A block of data words only (every block but the string's last) is read
+  // with plain loads: lane l's 32 bytes at 32 l, from the aligned dwords
+  // holding them (the one past them only when misaligned: it then holds
+  // their last bytes). The next block's loads are issued before this
+  // block's arithmetic.
+  const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
+  auto issue = [&](int64_t c, uint32_t* d) -> bool {
+    if (c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES > len) return false;
+    const uint64_t a4 = (uint64_t)(uintptr_t)(str + c * BLK_BYTES + 32 * lane) - sh;
+    const Q q0 = load16(gp16(a4)), q1 = load16(gp16(a4 + 16));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      d[u] = q0.d[u];
+      d[4 + u] = q1.d[u];
+    }
+    d[8] = sh ? *(const uint32_t*)gp16(a4 + 32) : 0u;
+    return true;
+  };
   A5 node;
   zero(node);
-  const int64_t c0 = n1 == 1 ? 0 : k * BLOCK;
-  const int64_t c1 = n1 == 1 ? 1 : (c0 + BLOCK < n1 ? c0 + BLOCK : n1);
-  F128 z1 = {0, 0, 0};
+  const int64_t c0 = k * BLOCK;
+  const int64_t c1 = c0 + BLOCK < n1 ? c0 + BLOCK : n1;
+  uint32_t dc[9], dn[9];
+  bool fc = issue(c0, dc);
   for (int64_t c = c0; c < c1; ++c) {
+    const bool fn = c + 1 < c1 && issue(c + 1, dn);
+    uint64_t x0, x1, y0, y1;
+    if (fc) {
+      uint32_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = align_bytes(dc[u + 1], dc[u], sh);
+      x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+      x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+      y0 = (uint64_t)x[4] | ((uint64_t)x[5] << 32);
+      y1 = (uint64_t)x[6] | ((uint64_t)x[7] << 32);
+    } else {  // the string's last block: padded, guarded reads
+      word128(str, len, c * BLOCK + 2 * lane, blo, bhi, &x0, &x1);
+      word128(str, len, c * BLOCK + 2 * lane + 1, blo, bhi, &y0, &y1);
+    }
     A5 sum;
     zero(sum);
-    uint64_t x0, x1;
-    word128(str, len, c * BLOCK + 2 * lane, blo, bhi, &x0, &x1);
     mac(sum, ka[0], ka[1], x0, x1);
-    word128(str, len, c * BLOCK + 2 * lane + 1, blo, bhi, &x0, &x1);
-    mac(sum, ka[2], ka[3], x0, x1);
+    mac(sum, ka[2], ka[3], y0, y1);
     wave_sum(sum);
     add_b(sum, A.keys, 1);
-    z1 = fold(sum);
+    const F128 z1 = fold(sum);
     uint64_t a0, a1;
     key_a(A.keys, 2, (uint32_t)(c % BLOCK), &a0, &a1);
     mac_fe(node, a0, a1, z1);
+#pragma unroll
+    for (int u = 0; u < 9; ++u) dc[u] = dn[u];
+    fc = fn;
   }
   if (lane != 0) return;
-  if (n1 == 1) {  // one block: the root is level 1
-    store128(A.out, A.flags, s, z1);
-    return;
-  }
   add_b(node, A.keys, 2);
   const F128 z2 = fold(node);
   if (n1 <= BLOCK) store128(A.out, A.flags, s, z2);  // one node: the root is level 2
   else if ((uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = z2;
+}
+
+// Strings of one block (at most 127 data words), eight lanes per string:
+// lane j sums words j, j + 8, ...; the eight partial sums are added, folded
+// and stored (the root is level 1).
+__global__ __launch_bounds__(256) void p128_short(P128Args A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = t / 8;
+  const int j = (int)(t % 8);
+  const bool act = s < A.count;
+  const int64_t len = act ? str_len(A.off, s, A.buf_bytes) : 0;
+  const bool mine = act && blocks_of(len) == 1;
+  A5 sum;
+  zero(sum);
+  if (mine) {
+    const uint8_t* str = A.buf + (len ? A.off[s] : 0);
+    const int64_t nw = len / W16 + 1;  // words, the pad's included
+    for (int64_t w = j; w < nw; w += 8) {
+      uint64_t x0, x1, a0, a1;
+      word128(str, len, w, A.buf, A.buf + A.buf_bytes, &x0, &x1);
+      key_a(A.keys, 1, (uint32_t)w, &a0, &a1);
+      mac(sum, a0, a1, x0, x1);
+    }
+  }
+  for (int m = 1; m < 8; m <<= 1) {  // every lane takes part in the shuffles
+    A5 o;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) o.w[i] = shx64(sum.w[i], m);
+    add(sum, o);
+  }
+  if (mine && j == 0) {
+    add_b(sum, A.keys, 1);
+    store128(A.out, A.flags, s, fold(sum));
+  }
 }
 
 // One wave per string with more than one level-2 node: levels 3 and up, each
@@ -341,6 +410,7 @@ hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* o
   hipError_t e = launch_excl_scan_u32(cnt, n, start, bsum, st);
   if (e != hipSuccess) return e;
   P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, start, z2, units_bound};
+  hipLaunchKernelGGL(p128_short, dim3(grid_for(count * 8)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_nodes, dim3(grid_for((int64_t)units_bound * 64)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_upper, dim3(grid_for(count * 64)), dim3(256), 0, st, a);
   return hipGetLastError();
