@@ -216,13 +216,10 @@ struct P128Args {
   uint64_t zcap;         // entries of z2 (only offsets that decrease can ask for more)
 };
 
-// One wave per unit (string, level-2 node), found by a 64-ary search of start.
-__global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
-  const int lane = (int)(threadIdx.x & 63u);
-  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  const int64_t units = A.start[A.count];
-  if (g >= units) return;
-  // the string s with start[s] <= g < start[s + 1]
+// The string s with start[s] <= g < start[s + 1] (strings without units
+// share their start with the next one, so the last such s): a 64-ary search
+// by the whole wave.
+__device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
   int64_t lo = 0, hi = A.count;
   while (hi - lo > 1) {
     const int64_t step = (hi - lo + 63) / 64;
@@ -233,7 +230,12 @@ __global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
     lo = lo + (int64_t)last * step;
     hi = lo + step < hi ? lo + step : hi;
   }
-  const int64_t s = lo;
+  return lo;
+}
+
+// Unit g: node k of string s.
+__device__ void node_unit(const P128Args& A, int64_t g, int lane) {
+  const int64_t s = unit_string(A, g, lane);
   const int64_t k = g - A.start[s];
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const uint8_t* str = A.buf + (len ? A.off[s] : 0);
@@ -305,6 +307,14 @@ __global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
   else if ((uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = z2;
 }
 
+// Persistent waves over the units (their number is start[count]).
+__global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t units = A.start[A.count];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw) node_unit(A, g, lane);
+}
+
 // Strings of one block (at most 127 data words), eight lanes per string:
 // lane j sums words j, j + 8, ...; the eight partial sums are added, folded
 // and stored (the root is level 1).
@@ -339,14 +349,11 @@ __global__ __launch_bounds__(256) void p128_short(P128Args A) {
   }
 }
 
-// One wave per string with more than one level-2 node: levels 3 and up, each
+// A string with more than one level-2 node: levels 3 and up by one wave, each
 // level's values written over the previous ones (node q's value goes to
 // index q, below its first input 128 q once q > 0, and node 0 is read before
 // it is written).
-__global__ __launch_bounds__(256) void p128_upper(P128Args A) {
-  const int lane = (int)(threadIdx.x & 63u);
-  const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  if (s >= A.count) return;
+__device__ void climb_string(const P128Args& A, int64_t s, int lane) {
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const int64_t n1 = blocks_of(len);
   if (n1 <= BLOCK) return;
@@ -376,6 +383,17 @@ __global__ __launch_bounds__(256) void p128_upper(P128Args A) {
     n = nout;
   }
   if (lane == 0) store128(A.out, A.flags, s, v[0]);
+}
+
+// Persistent waves over the units; a string's first unit climbs it.
+__global__ __launch_bounds__(256) void p128_upper(P128Args A) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t units = A.start[A.count];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw) {
+    const int64_t s = unit_string(A, g, lane);
+    if (g == A.start[s]) climb_string(A, s, lane);
+  }
 }
 
 unsigned grid_for(int64_t threads) {
@@ -410,9 +428,11 @@ hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* o
   hipError_t e = launch_excl_scan_u32(cnt, n, start, bsum, st);
   if (e != hipSuccess) return e;
   P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, start, z2, units_bound};
+  // persistent grids: at most 8192 waves, fewer when the units are fewer
+  const int64_t waves = units_bound < 8192 ? (int64_t)units_bound : 8192;
   hipLaunchKernelGGL(p128_short, dim3(grid_for(count * 8)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(p128_nodes, dim3(grid_for((int64_t)units_bound * 64)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(p128_upper, dim3(grid_for(count * 64)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(p128_nodes, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(p128_upper, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
