@@ -12,13 +12,14 @@
 // (adding 51 p keeps every term non-negative), which is below 53 * 2^128;
 // one more step v0 - 51 v1 (plus p when negative) lands in [0, p).
 //
-// Launches: (1) the number of level-2 nodes of each string of more than one
-// block and an exclusive scan of those counts; (2) strings of one block,
-// eight lanes each; (3) one wave per (string, level-2 node): lane l forms
-// words 2l and 2l + 1 of each of the node's blocks, the block's exact sum is
-// reduced over the wave and folded, and the node sums a_{2,i} z_i; a string
-// of one node is finished here; (4) one wave per longer string climbs its
-// level-2 values (levels 3 and up) in place.
+// Launches: (1) the number of units of each string of more than one block
+// (a unit is a quarter of a level-2 node: 32 blocks) and an exclusive scan
+// of those counts; (2) strings of one block, eight lanes each; (3) one wave
+// per unit: lane l forms words 2l and 2l + 1 of each of the unit's blocks,
+// the block's exact sum is reduced over the wave and folded, and the unit's
+// share of its node, sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
+// per string of more than one block adds each node's quarters and b_2 and
+// climbs the levels above 2 in place.
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
 
@@ -29,6 +30,7 @@ namespace {
 constexpr uint64_t K128 = 51;
 constexpr int W16 = 16;                      // bytes per word
 constexpr uint64_t BLK_BYTES = BLOCK * W16;  // 2 KiB per level-1 block
+constexpr int QB = 32;                       // blocks per unit: a quarter of a level-2 node
 
 struct A5 {
   uint64_t w[5];
@@ -173,11 +175,11 @@ __device__ __forceinline__ void word128(const uint8_t* s, int64_t len, int64_t w
 }
 
 __device__ __forceinline__ int64_t blocks_of(int64_t len) { return (len / W16 + 1 + BLOCK - 1) / BLOCK; }
-// units of the node kernel: level-2 nodes; strings of one block have none
-// (the short-string kernel takes them)
+// units of the node kernel: quarters of level-2 nodes (QB blocks); strings
+// of one block have none (the short-string kernel takes them)
 __device__ __forceinline__ int64_t units_of(int64_t len) {
   const int64_t n1 = blocks_of(len);
-  return n1 == 1 ? 0 : (n1 + BLOCK - 1) / BLOCK;
+  return n1 == 1 ? 0 : (n1 + QB - 1) / QB;
 }
 
 __device__ __forceinline__ int64_t str_len(const int64_t* off, int64_t i, uint64_t buf_bytes) {
@@ -233,7 +235,7 @@ __device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
   return lo;
 }
 
-// Unit g: node k of string s.
+// Unit g: quarter k of string s's level-2 nodes (blocks QB k ..).
 __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
   const int64_t s = unit_string(A, g, lane);
   const int64_t k = g - A.start[s];
@@ -267,8 +269,8 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
   };
   A5 node;
   zero(node);
-  const int64_t c0 = k * BLOCK;
-  const int64_t c1 = c0 + BLOCK < n1 ? c0 + BLOCK : n1;
+  const int64_t c0 = k * QB;
+  const int64_t c1 = c0 + QB < n1 ? c0 + QB : n1;
   uint32_t dc[9], dn[9];
   bool fc = issue(c0, dc);
   for (int64_t c = c0; c < c1; ++c) {
@@ -300,11 +302,8 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
     for (int u = 0; u < 9; ++u) dc[u] = dn[u];
     fc = fn;
   }
-  if (lane != 0) return;
-  add_b(node, A.keys, 2);
-  const F128 z2 = fold(node);
-  if (n1 <= BLOCK) store128(A.out, A.flags, s, z2);  // one node: the root is level 2
-  else if ((uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = z2;
+  // the quarter's share of its node, reduced (b_2 is added with the node)
+  if (lane == 0 && (uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = fold(node);
 }
 
 // Persistent waves over the units (their number is start[count]).
@@ -349,17 +348,36 @@ __global__ __launch_bounds__(256) void p128_short(P128Args A) {
   }
 }
 
-// A string with more than one level-2 node: levels 3 and up by one wave, each
-// level's values written over the previous ones (node q's value goes to
-// index q, below its first input 128 q once q > 0, and node 0 is read before
-// it is written).
+__device__ __forceinline__ void add_fe(A5& s, const F128& z) {
+  add_at(s, (u128)z.lo | ((u128)z.hi << 64), 0);
+  if (z.top) add_at(s, (u128)1, 2);
+}
+
+// A string of more than one block, by one wave: its level-2 nodes from their
+// quarters (node k = the sum of quarters 4k .. 4k + 3 plus b_2), then levels
+// 3 and up. Each step writes its values over the previous ones: value q goes
+// to index q, at or below its first input; a wave's loads of a step are done
+// before its stores, and steps are ordered by a fence.
 __device__ void climb_string(const P128Args& A, int64_t s, int lane) {
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const int64_t n1 = blocks_of(len);
-  if (n1 <= BLOCK) return;
-  int64_t n = (n1 + BLOCK - 1) / BLOCK;  // level-2 values
-  if ((uint64_t)(A.start[s] + n) > A.zcap) return;
+  if (n1 == 1) return;
+  const int64_t nq = (n1 + QB - 1) / QB;  // quarter values
+  if ((uint64_t)(A.start[s] + nq) > A.zcap) return;
   F128* v = A.z2 + A.start[s];
+  int64_t n = (n1 + BLOCK - 1) / BLOCK;  // level-2 values
+  for (int64_t k0 = 0; k0 < n; k0 += 64) {
+    const int64_t k = k0 + lane;
+    A5 sum;
+    zero(sum);
+    if (k < n) {
+      for (int64_t u = 4 * k; u < 4 * k + 4 && u < nq; ++u) add_fe(sum, v[u]);
+      add_b(sum, A.keys, 2);
+    }
+    __threadfence();  // every lane has read its quarters
+    if (k < n) v[k] = fold(sum);
+    __threadfence();
+  }
   for (int j = 3; n > 1 && j <= LMAX; ++j) {
     const int64_t nout = (n + BLOCK - 1) / BLOCK;
     for (int64_t q = 0; q < nout; ++q) {
@@ -407,7 +425,7 @@ unsigned grid_for(int64_t threads) {
 // and one), the scan's tile totals, then 32 bytes per possible unit
 uint64_t pm128_scratch_bytes(int64_t count, uint64_t buf_bytes) {
   const uint64_t n = (uint64_t)count;
-  const uint64_t units = 2 * n + buf_bytes / (BLK_BYTES * BLOCK) + 2;
+  const uint64_t units = 2 * n + buf_bytes / (BLK_BYTES * QB) + 2;
   return ((4 * n + 7) & ~7ull) + 8 * (n + 1) + excl_scan_work_bytes(n) + sizeof(F128) * units;
 }
 
@@ -422,7 +440,7 @@ hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* o
   uint64_t* bsum = (uint64_t*)p;
   p += excl_scan_work_bytes(n);
   F128* z2 = (F128*)p;
-  const uint64_t units_bound = 2 * n + buf_bytes / (BLK_BYTES * BLOCK) + 2;
+  const uint64_t units_bound = 2 * n + buf_bytes / (BLK_BYTES * QB) + 2;
   hipLaunchKernelGGL(p128_count, dim3(grid_for(count) > 65536 ? 65536 : grid_for(count)), dim3(256), 0, st, offsets,
                      count, buf_bytes, cnt);
   hipError_t e = launch_excl_scan_u32(cnt, n, start, bsum, st);
