@@ -51,11 +51,18 @@ DESCR = {
 }
 
 
+KERNEL_SOURCES = {
+    "pmp_kernels.hip": ("pmp_kernels.hip", "pmp_device.hpp", "pmp_batch.h"),
+    "pmp_incr.hip": ("pmp_incr.hip", "pmp_device.hpp", "pmp_batch.h", "pmp_incr.h"),
+}
+
+
 def kernel_source_hash(main: str = "pmp_kernels.hip") -> str:
-    """sha256 (first 16 hex digits) of a kernel file and the device headers
-    with their comments and blank lines removed: edits to comments keep it."""
+    """sha256 (first 16 hex digits) of a kernel file and the headers it is
+    compiled from, with comments and blank lines removed: edits to comments
+    keep it."""
     h = hashlib.sha256()
-    for f in (main, "pmp_device.hpp", "pmp_internal.h"):
+    for f in KERNEL_SOURCES[main]:
         with open(os.path.join(ROOT, "paper_1609_09840_amd", "csrc", f), encoding="utf-8") as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         for line in text.splitlines():

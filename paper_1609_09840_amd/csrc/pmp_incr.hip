@@ -27,7 +27,7 @@
 // level with a single node. It reads the state without changing it, so more
 // pieces may follow.
 #include "pmp_device.hpp"
-#include "pmp_internal.h"
+#include "pmp_incr.h"
 
 namespace pmp {
 

@@ -5,91 +5,10 @@
 #include <stdint.h>
 
 #include "pmp.h"
+#include "pmp_batch.h"
+#include "pmp_incr.h"
 
 namespace pmp {
-
-constexpr uint32_t FLAG_NO_MIX = 1u;
-constexpr uint32_t FLAG_OUT_FIELD = 2u;
-
-constexpr int32_t STATUS_OFFSETS = 1;   // an offsets pair was out of order or out of range
-constexpr int32_t STATUS_INTERNAL = 2;  // a node accumulator fell outside the workspace
-
-// Accumulator of one tree node (level >= 2), all zero between launches.
-// PM+32: w0 = (weight received << 56) | sum of field elements (< 2^40).
-// PM+64: w0 = low 64 bits of the sum, w1 = (weight << 32) | high bits.
-struct Slot {
-  uint64_t w0;
-  uint64_t w1;
-};
-
-// One batch as the kernel sees it.
-struct BatchArgs {
-  const uint8_t* buf;
-  uint64_t buf_bytes;
-  const int64_t* offsets;
-  int64_t count;
-  const void* keys;  // uint32[1032] (PM+32) or uint64[1032] (PM+64)
-  void* out;
-  uint32_t flags;
-  uint32_t wide;
-  Slot* slots;  // ceil(buf_bytes / (128 W)) + 2 node accumulators
-  uint64_t nslots;
-  uint64_t work0;  // work of the batches before this one
-  uint64_t work;   // alpha * count + buf_bytes
-};
-
-// The work of a launch is the sum over batches of alpha * count + buf_bytes:
-// string i of a batch starts at work position work0 + alpha * i + offsets[i]
-// (a byte of buffer and a string each count as work). The work is cut into
-// per_wave * total_waves shares of `share` units; wave w takes shares w,
-// w + total_waves, w + 2 total_waves, ...
-struct KArgs {
-  BatchArgs b[2];              // up to two batches travel in the arguments...
-  const BatchArgs* batches;    // ...more come as a device array (else null)
-  uint32_t nbatch;
-  uint32_t alpha;        // per-string work in byte equivalents
-  int32_t* status;       // device status word (STATUS_* bits)
-  uint32_t total_waves;  // waves sharing the work
-  uint32_t per_wave;     // shares per wave
-  uint64_t total;        // work of all batches
-  uint64_t share;        // work per share
-};
-
-// Incremental hashing of one string delivered in pieces (the streaming form
-// of Algorithm 1: one open node per level, Sec. 4). Device-resident; all
-// zero after creation and reset.
-//   part[j] (j = 2..8): exact sum sum_i a_{j,i} z_i over the level-(j-1)
-//     values z already produced for the open level-j node (b_j not added);
-//     3 words (PM+32: lo, hi, 0; PM+64: w0, w1, w2), the fourth unused.
-//   carry: the bytes of the open level-1 block (fewer than 128 W).
-struct IncrState {
-  uint64_t part[9][4];
-  uint32_t carry[(1024 + 16) / 4];
-};
-
-// One append that completes at least one level-1 block. The piece's bytes
-// follow the t carried bytes; blocks s1 .. s1 + k - 1 (numbered from the
-// string's start) are completed by it; r_new bytes are carried afterwards.
-// Workgroup w of the first launch takes segment s1 / 32 + w (32 blocks, a
-// quarter of a level-2 node). Per level-2 node touched (numbered from node
-// s1 / 128): an accumulator Slot for its segments (0 between launches).
-constexpr int INCR_SEG = 32;
-struct IncrArgs {
-  const uint8_t* piece;
-  int64_t n;
-  uint64_t s1;
-  uint64_t k;
-  uint32_t t;
-  uint32_t r_new;
-  uint32_t nwg;
-  uint32_t pad_;
-  const void* keys;
-  IncrState* st;
-  uint4* za;        // level outputs, ping-pong: each `cap` entries
-  uint4* zb;
-  Slot* slots;      // per node touched
-  uint64_t* sums;   // sums of the first and last level-2 nodes, when open (2 x 4 words)
-};
 
 // host side (pmp_api.cpp)
 int set_error(int code, const char* msg);  // sets the message pmp_last_error returns

@@ -27,7 +27,7 @@
 // (its own atomic's result carries the data dependency), computes the node,
 // returns the slot to zero and climbs on.
 #include "pmp_device.hpp"
-#include "pmp_internal.h"
+#include "pmp_batch.h"
 
 namespace pmp {
 
