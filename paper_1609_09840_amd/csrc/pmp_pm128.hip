@@ -14,7 +14,7 @@
 //
 // Launches: (1) the number of units of each string of more than one block
 // (a unit is a quarter of a level-2 node: 32 blocks) and an exclusive scan
-// of those counts; (2) strings of one block, eight lanes each; (3) one wave
+// of those counts; (2) strings of one block, four lanes each; (3) one wave
 // per unit: lane l forms words 2l and 2l + 1 of each of the unit's blocks,
 // the block's exact sum is reduced over the wave and folded, and the unit's
 // share of its node, sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
@@ -314,13 +314,17 @@ __global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
   for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw) node_unit(A, g, lane);
 }
 
-// Strings of one block (at most 127 data words), eight lanes per string:
-// lane j sums words j, j + 8, ...; the eight partial sums are added, folded
-// and stored (the root is level 1).
+// Strings of one block (at most 127 data words), SL lanes per string: lane
+// j sums words j, j + SL, ...; the partial sums are added over the lanes,
+// folded and stored (the root is level 1). A word wholly inside the string
+// is read with plain loads of the aligned dwords holding it (the one past it
+// only when misaligned); the word holding the pad is formed with guarded
+// reads.
+constexpr int SL = 4;
 __global__ __launch_bounds__(256) void p128_short(P128Args A) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = t / 8;
-  const int j = (int)(t % 8);
+  const int64_t s = t / SL;
+  const int j = (int)(t % SL);
   const bool act = s < A.count;
   const int64_t len = act ? str_len(A.off, s, A.buf_bytes) : 0;
   const bool mine = act && blocks_of(len) == 1;
@@ -328,15 +332,28 @@ __global__ __launch_bounds__(256) void p128_short(P128Args A) {
   zero(sum);
   if (mine) {
     const uint8_t* str = A.buf + (len ? A.off[s] : 0);
+    const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
     const int64_t nw = len / W16 + 1;  // words, the pad's included
-    for (int64_t w = j; w < nw; w += 8) {
+    for (int64_t w = j; w < nw; w += SL) {
       uint64_t x0, x1, a0, a1;
-      word128(str, len, w, A.buf, A.buf + A.buf_bytes, &x0, &x1);
+      if (W16 * w + W16 <= len) {
+        const uint64_t a4 = (uint64_t)(uintptr_t)(str + W16 * w) - sh;
+        const Q q = load16(gp16(a4));
+        const uint32_t d4 = sh ? *(const uint32_t*)gp16(a4 + 16) : 0u;
+        const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], d4};
+        uint32_t x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
+        x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+        x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+      } else {
+        word128(str, len, w, A.buf, A.buf + A.buf_bytes, &x0, &x1);
+      }
       key_a(A.keys, 1, (uint32_t)w, &a0, &a1);
       mac(sum, a0, a1, x0, x1);
     }
   }
-  for (int m = 1; m < 8; m <<= 1) {  // every lane takes part in the shuffles
+  for (int m = 1; m < SL; m <<= 1) {  // every lane takes part in the shuffles
     A5 o;
 #pragma unroll
     for (int i = 0; i < 5; ++i) o.w[i] = shx64(sum.w[i], m);
@@ -448,7 +465,7 @@ hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* o
   P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, start, z2, units_bound};
   // persistent grids: at most 8192 waves, fewer when the units are fewer
   const int64_t waves = units_bound < 8192 ? (int64_t)units_bound : 8192;
-  hipLaunchKernelGGL(p128_short, dim3(grid_for(count * 8)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(p128_short, dim3(grid_for(count * SL)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_nodes, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_upper, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   return hipGetLastError();
