@@ -274,7 +274,7 @@ def plain_gpu(keep, dev, max_strings: int = 4000):
 def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20), reps: int = 3) -> dict:
     """One string of `total` bytes appended in equal pieces, then a digest.
     HIP events on the object's stream: one pair around the appends of a pass
-    (per-append time = its share; an append is two launches), one more after
+    (per-append time = its share; an append is one launch), one more after
     the digest; `reps` passes after a warm one, each after a reset. The digest
     must equal pmp_hash32/64 of the string. `roofline`: the largest pieces'
     append rate against the HBM peak (algorithmic bytes = the piece)."""
@@ -320,7 +320,7 @@ def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20)
         h.close()
     big = [r for r in res["runs"] if r["piece_bytes"] == max(pieces)]
     best = max(big, key=lambda r: r["append_GBps"])
-    res["roofline"] = {"bound": "hbm", "kernel": "incr_blocks + incr_tree (one append)",
+    res["roofline"] = {"bound": "hbm", "kernel": "incr_blocks (one append)",
                        "variant": best["variant"], "piece_bytes": best["piece_bytes"],
                        "achieved": best["append_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(best["append_GBps"] / HBM_PEAK_GBS, 4),

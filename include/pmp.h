@@ -348,14 +348,15 @@ int pmp_table_probe(pmp_plan* plan, const pmp_batch* queries, const pmp_batch* k
  * pmp_incr_create: wide = 0 (PM+32) or 1 (PM+64); d_keys is the device key
  * table (1032 uint32 or uint64), which must stay valid and unchanged for
  * the object's life. Every call on the object is queued on `stream`, in
- * order. Allocates about 1.5 KiB of device state plus a workspace (16 bytes
- * per 64 KiB (PM+32) or 128 KiB (PM+64) of the largest piece). Returns
- * PMP_E_INVALID_ARG or PMP_E_NOMEM.
+ * order. Allocates about 1.5 KiB of device state plus a workspace of 80
+ * bytes per level-2 node of the largest piece (a node is 64 KiB of PM+32 or
+ * 128 KiB of PM+64 input). Returns PMP_E_INVALID_ARG or PMP_E_NOMEM.
  *
  * pmp_incr_append: appends nbytes device bytes at d_piece (any alignment;
  * nbytes = 0 is a no-op). Asynchronous: the piece must stay unchanged until
- * the stream has passed the call. Two launches (one when the piece completes
- * no 128-word block: its bytes are only carried). A piece larger than any before
+ * the stream has passed the call. One launch, which also finishes the tree
+ * levels of the previous append (an append's levels above 1 run at the start
+ * of the next append or digest). A piece larger than any before
  * (beyond what pmp_incr_reserve set aside) first synchronizes the stream and
  * grows the workspace. Returns PMP_E_TOO_LONG if the string would need more
  * than 8 levels (more than 128^8 words after padding), leaving the state as
@@ -363,7 +364,8 @@ int pmp_table_probe(pmp_plan* plan, const pmp_batch* queries, const pmp_batch* k
  *
  * pmp_incr_digest: writes the hash of everything appended so far to d_out
  * (one output in the layout of pmp_hash32 / pmp_hash64 for these flags).
- * The state is not changed: more pieces may follow. One launch.
+ * More pieces may follow (the digest only runs the last append's pending
+ * tree levels, as the next append would). One launch.
  *
  * pmp_incr_reset: starts a new string with the same keys.
  * pmp_incr_length: bytes appended since creation or the last reset.

@@ -814,12 +814,15 @@ struct pmp_incr {
   int wide = 0;
   const void* keys = nullptr;
   hipStream_t stream = nullptr;
-  pmp::IncrState* st = nullptr;  // device state, followed by the two boundary sums
+  pmp::IncrState* st = nullptr;  // device state, followed by two sets of boundary sums
   uint64_t* sums = nullptr;
-  uint4* z = nullptr;            // two level-output buffers of cap entries each, then
-                                 // cap node accumulators
+  uint4* z = nullptr;            // per parity two level-output buffers of cap entries,
+                                 // then cap node accumulators
   uint64_t cap = 0;
   uint64_t len = 0;              // bytes appended since creation or reset
+  int parity = 0;                // buffers of the next append that completes blocks
+  bool pending = false;          // the last such append's tree step has not run yet
+  uint64_t p_s1 = 0, p_k = 0;    // that append's blocks
 };
 
 namespace {
@@ -832,13 +835,25 @@ uint64_t incr_nodes_for(const pmp_incr* h, uint64_t n) {
 }
 
 size_t incr_workspace_bytes(uint64_t entries) {
-  return entries * (2 * sizeof(uint4) + sizeof(pmp::Slot));
+  return entries * (4 * sizeof(uint4) + sizeof(pmp::Slot));
+}
+
+// the tree step left by the last append that completed blocks
+pmp::IncrTree incr_prev(const pmp_incr* h) {
+  const int q = h->parity ^ 1;
+  return pmp::IncrTree{h->p_s1, h->p_k, h->z + 2 * q * h->cap, h->z + (2 * q + 1) * h->cap, h->sums + 8 * q};
 }
 
 int incr_grow(pmp_incr* h, uint64_t entries) {
   if (entries <= h->cap) return PMP_OK;
+  hipError_t e;
+  if (h->pending) {  // the pending tree step reads the old buffers
+    e = pmp::launch_incr_flush(h->wide, h->st, h->keys, incr_prev(h), h->stream);
+    if (e != hipSuccess) return hip_fail(e, "tree step launch");
+    h->pending = false;
+  }
   // queued appends may still use the old buffers
-  hipError_t e = hipStreamSynchronize(h->stream);
+  e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   if (h->z) {
     e = hipFree(h->z);
@@ -874,7 +889,7 @@ int pmp_incr_create(int wide, const void* d_keys, pmp_stream_t stream, pmp_incr*
   h->keys = d_keys;
   h->stream = (hipStream_t)stream;
   void* mem = nullptr;
-  hipError_t e = hipMalloc(&mem, sizeof(pmp::IncrState) + 8 * sizeof(uint64_t));
+  hipError_t e = hipMalloc(&mem, sizeof(pmp::IncrState) + 16 * sizeof(uint64_t));
   if (e != hipSuccess) {
     delete h;
     return fail(PMP_E_NOMEM, "incremental state: %s", hipGetErrorString(e));
@@ -934,12 +949,19 @@ int pmp_incr_append(pmp_incr* h, const uint8_t* d_piece, uint64_t nbytes) {
     a.nwg = (uint32_t)nwg;
     a.keys = h->keys;
     a.st = h->st;
-    a.za = h->z;
-    a.zb = h->z + h->cap;
-    a.slots = (pmp::Slot*)(h->z + 2 * h->cap);
-    a.sums = h->sums;
+    const int q = h->parity;
+    a.za = h->z + 2 * q * h->cap;
+    a.zb = h->z + (2 * q + 1) * h->cap;
+    a.slots = (pmp::Slot*)(h->z + 4 * h->cap);
+    a.sums = h->sums + 8 * q;
+    a.pending = h->pending ? 1u : 0u;
+    a.prev = incr_prev(h);
     e = pmp::launch_incr_append(h->wide, a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "append launch");
+    h->pending = true;
+    h->p_s1 = s1;
+    h->p_k = k;
+    h->parity ^= 1;
   }
   h->len = len1;
   return PMP_OK;
@@ -954,8 +976,9 @@ int pmp_incr_digest(pmp_incr* h, void* d_out, uint32_t flags) {
   nodes[1] = h->len / C + 1;  // the open block holds at least the pad word
   for (int j = 2; j <= PMP_LEVELS; ++j) nodes[j] = (nodes[j - 1] + PMP_BLOCK - 1) / PMP_BLOCK;
   hipError_t e = pmp::launch_incr_digest(h->wide, h->st, (uint32_t)(h->len % C), nodes, h->keys, d_out, flags,
-                                         h->stream);
+                                         h->pending ? 1u : 0u, incr_prev(h), h->stream);
   if (e != hipSuccess) return hip_fail(e, "digest launch");
+  h->pending = false;  // the digest ran it
   return PMP_OK;
 }
 
@@ -964,6 +987,7 @@ int pmp_incr_reset(pmp_incr* h) {
   hipError_t e = pmp::launch_incr_reset(h->st, h->stream);
   if (e != hipSuccess) return hip_fail(e, "state reset");
   h->len = 0;
+  h->pending = false;
   return PMP_OK;
 }
 

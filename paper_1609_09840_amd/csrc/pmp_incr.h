@@ -17,12 +17,25 @@ struct IncrState {
   uint32_t carry[(1024 + 16) / 4];
 };
 
+// The tree step of an append that completed blocks s1 .. s1 + k - 1: its
+// first and last level-2 nodes with the open sums, and the levels above 2.
+// It runs at the start of the next launch on the string (next append or
+// digest), so an append is one launch.
+struct IncrTree {
+  uint64_t s1;
+  uint64_t k;
+  uint4* za;        // that append's level-2 values, then level outputs (ping-pong with zb)
+  uint4* zb;
+  uint64_t* sums;   // its first and last level-2 node sums, when open (2 x 4 words)
+};
+
 // One append that completes at least one level-1 block. The piece's bytes
 // follow the t carried bytes; blocks s1 .. s1 + k - 1 (numbered from the
 // string's start) are completed by it; r_new bytes are carried afterwards.
-// Workgroup w of the first launch takes segment s1 / 32 + w (32 blocks, a
-// quarter of a level-2 node). Per level-2 node touched (numbered from node
-// s1 / 128): an accumulator Slot for its segments (0 between launches).
+// Workgroup w takes segment s1 / 32 + w (32 blocks, a quarter of a level-2
+// node). Per level-2 node touched (numbered from node s1 / 128): an
+// accumulator Slot for its segments (0 between launches). Workgroup 0 first
+// runs the previous append's tree step when `pending`.
 constexpr int INCR_SEG = 32;
 struct IncrArgs {
   const uint8_t* piece;
@@ -39,6 +52,8 @@ struct IncrArgs {
   uint4* zb;
   Slot* slots;      // per node touched
   uint64_t* sums;   // sums of the first and last level-2 nodes, when open (2 x 4 words)
+  uint32_t pending; // prev holds a tree step still to run
+  IncrTree prev;
 };
 
 }  // namespace pmp

@@ -7,20 +7,24 @@
 // open level-j node. Because Eq. (1) is a sum of products, the values need not
 // be kept: each is multiplied by its key as soon as it exists.
 //
-// An append that completes level-1 blocks is two launches. In the first,
-// workgroup w takes the w-th segment of 32 blocks (aligned to the string's
-// start) that the piece touches: 32 groups of 8 lanes, one block per group,
-// each lane loading the 16-byte pieces j, j + 8, ... of its block at once. A
-// block is summed exactly over its 8 lanes, folded into a field element
-// (Sec. 6.2 and Algorithm 2) and multiplied by its level-2 key; the
-// workgroup adds its 32 products and, when other segments share the node,
-// adds the reduced sum into the node's accumulator with relaxed atomics (no
-// fences: a device-scope release writes back the whole L2). The segment that
-// completes a node finishes it if all its blocks lie in the piece. The
-// second launch (one workgroup) completes the first and last level-2 nodes
-// with the state's open sums, stores the new open sums and carried bytes,
-// and climbs the levels above 2 (at most 1/128 of the level-2 values), one
-// wave per node.
+// An append that completes level-1 blocks is one launch. Workgroup w takes
+// the w-th segment of 32 blocks (aligned to the string's start) that the
+// piece touches: 32 groups of 8 lanes, one block per group, each lane loading
+// the 16-byte pieces j, j + 8, ... of its block at once. A block is summed
+// exactly over its 8 lanes, folded into a field element (Sec. 6.2 and
+// Algorithm 2) and multiplied by its level-2 key; the workgroup adds its 32
+// products and, when other segments share the node, adds the reduced sum
+// into the node's accumulator with relaxed atomics (no fences: a
+// device-scope release writes back the whole L2). The segment that completes
+// a node finishes it if all its blocks lie in the piece. Workgroup 0 also
+// stages the block that begins in the carried bytes and stores the bytes
+// carried to the next piece. The append's tree step (its first and last
+// level-2 nodes with the state's open sums, then levels 3 and up, at most
+// 1/128 of the level-2 values, one wave per node) needs every workgroup's
+// results, so it runs at the start of the next launch on the string:
+// workgroup 0 of the next append, or the digest. Level outputs and boundary
+// sums alternate between two buffers, so that an append's tree step reads
+// what the next append does not write.
 //
 // A digest pads the open block (end of Sec. 4), hashes it and climbs through
 // the open nodes to the root: the do-while of Algorithm 1 stops at the first
@@ -118,6 +122,61 @@ __device__ uint64_t climb(IncrState* st, const typename Tr<WIDE>::key_t* keys, i
   return (s_in + n_in) / BLOCK - q0;
 }
 
+// The tree step of an append (one workgroup, all threads): the level-2 nodes
+// that its piece shares with the string before or after it, then the levels
+// above 2.
+template <bool WIDE>
+__device__ void tree_step(IncrState* st, const typename Tr<WIDE>::key_t* keys, const IncrTree& T, uint64_t* pend) {
+  using S = typename Tr<WIDE>::Sum;
+  if (threadIdx.x == 0) {
+    const bool start_open = T.s1 % BLOCK != 0;
+    const bool end_open = (T.s1 + T.k) % BLOCK != 0;
+    const bool one = T.s1 / BLOCK == (T.s1 + T.k - 1) / BLOCK;
+    uint64_t np[3] = {0, 0, 0};
+    if (start_open || (one && end_open)) {
+      S x;
+      from_words(x, T.sums);
+      if (start_open) {
+        S o;
+        from_words(o, st->part[2]);
+        add(x, o);
+      }
+      if (!(one && end_open)) T.za[0] = pack(finish<WIDE>(x, keys, 2));
+      else to_words(x, np);
+    }
+    if (!one && end_open) {
+      np[0] = T.sums[4];
+      np[1] = T.sums[5];
+      np[2] = T.sums[6];
+    }
+    st->part[2][0] = np[0];
+    st->part[2][1] = np[1];
+    st->part[2][2] = np[2];
+  }
+  __syncthreads();
+
+  uint64_t n_in = (T.s1 + T.k) / BLOCK - T.s1 / BLOCK;  // complete level-2 nodes
+  uint64_t s_in = T.s1 / BLOCK;                         // level-2 values before that piece
+  uint4* in = T.za;
+  uint4* out = T.zb;
+  for (int lvl = 3; lvl <= LMAX && n_in > 0; ++lvl) {
+    const uint64_t n_out = climb<WIDE>(st, keys, lvl, in, n_in, s_in, out, pend);
+    s_in /= BLOCK;
+    n_in = n_out;
+    uint4* t = in;
+    in = out;
+    out = t;
+  }
+}
+
+// A pending tree step on its own (before the workspace that holds its values
+// is replaced).
+template <bool WIDE>
+__global__ __launch_bounds__(256) void incr_flush(IncrState* st, const void* keys, IncrTree T) {
+  __shared__ uint64_t pend[3];
+  tree_step<WIDE>(st, (const typename Tr<WIDE>::key_t*)keys, T, pend);
+}
+
 // Add field element v, with weight 1, into a node accumulator whose
 // segments in this launch number `target`; the call that brings the weight
 // to `target` gets the total (lo + 2^64 hi, at most four field elements) and
@@ -162,9 +221,11 @@ __global__ __launch_bounds__(256) void incr_blocks(IncrArgs A) {
   static_assert(256 / GL == INCR_SEG, "one block per group of lanes");
   __shared__ uint32_t stg[C / 4];     // the block that begins in the carried bytes
   __shared__ uint64_t red[INCR_SEG][3];
+  __shared__ uint64_t pend[3];
 
   const K* keys = (const K*)A.keys;
   const int tid = (int)threadIdx.x, g = tid / GL, j = tid % GL;
+  if (blockIdx.x == 0 && A.pending) tree_step<WIDE>(A.st, keys, A.prev, pend);
   const uint64_t sg0 = A.s1 / INCR_SEG, sg1 = (A.s1 + A.k - 1) / INCR_SEG;
   const uint64_t sg = sg0 + blockIdx.x;  // this workgroup's segment
   const uint64_t c = sg * INCR_SEG + g;  // this group's block
@@ -177,6 +238,11 @@ __global__ __launch_bounds__(256) void incr_blocks(IncrArgs A) {
     const uint8_t* cb = (const uint8_t*)A.st->carry;
     for (int p = tid; p < C; p += 256) s8[p] = p < (int)A.t ? cb[p] : A.piece[p - (int)A.t];
     __syncthreads();
+  }
+  if (blockIdx.x == 0) {  // the bytes carried to the next piece (the old ones are staged)
+    uint8_t* cb = (uint8_t*)A.st->carry;
+    const uint8_t* src = A.piece + (A.n - (int64_t)A.r_new);
+    for (uint32_t p = (uint32_t)tid; p < A.r_new; p += 256) cb[p] = src[p];
   }
 
   // this lane's pieces of the block: all loads first
@@ -277,82 +343,29 @@ __global__ __launch_bounds__(256) void incr_blocks(IncrArgs A) {
   else to_words(tot, A.sums + 4 * (slot == 0 ? 0 : 1));  // first or last node, open
 }
 
-// Second launch of an append, one workgroup: the level-2 nodes that the
-// piece shares with the string before or after it, the carried bytes, then
-// the levels above 2.
-template <bool WIDE>
-__global__ __launch_bounds__(256) void incr_tree(IncrArgs A) {
-  using S = typename Tr<WIDE>::Sum;
-  using K = typename Tr<WIDE>::key_t;
-  __shared__ uint64_t pend[3];
-  const K* keys = (const K*)A.keys;
-  const int tid = (int)threadIdx.x;
-  if (tid == 0) {
-    IncrState* st = A.st;
-    const bool start_open = A.s1 % BLOCK != 0;
-    const bool end_open = (A.s1 + A.k) % BLOCK != 0;
-    const bool one = A.s1 / BLOCK == (A.s1 + A.k - 1) / BLOCK;
-    uint64_t np[3] = {0, 0, 0};
-    if (start_open || (one && end_open)) {
-      S x;
-      from_words(x, A.sums);
-      if (start_open) {
-        S o;
-        from_words(o, st->part[2]);
-        add(x, o);
-      }
-      if (!(one && end_open)) A.za[0] = pack(finish<WIDE>(x, keys, 2));
-      else to_words(x, np);
-    }
-    if (!one && end_open) {
-      np[0] = A.sums[4];
-      np[1] = A.sums[5];
-      np[2] = A.sums[6];
-    }
-    st->part[2][0] = np[0];
-    st->part[2][1] = np[1];
-    st->part[2][2] = np[2];
-  }
-  // the bytes carried to the next piece
-  {
-    uint8_t* cb = (uint8_t*)A.st->carry;
-    const uint8_t* src = A.piece + (A.n - (int64_t)A.r_new);
-    for (uint32_t p = (uint32_t)tid; p < A.r_new; p += 256) cb[p] = src[p];
-  }
-  __syncthreads();
-
-  uint64_t n_in = (A.s1 + A.k) / BLOCK - A.s1 / BLOCK;  // complete level-2 nodes
-  uint64_t s_in = A.s1 / BLOCK;                         // level-2 values before this piece
-  uint4* in = A.za;
-  uint4* out = A.zb;
-  for (int lvl = 3; lvl <= LMAX && n_in > 0; ++lvl) {
-    const uint64_t n_out = climb<WIDE>(A.st, keys, lvl, in, n_in, s_in, out, pend);
-    s_in /= BLOCK;
-    n_in = n_out;
-    uint4* t = in;
-    in = out;
-    out = t;
-  }
-}
-
 // An append that completes no block: its bytes join the carried ones.
 __global__ void incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, int64_t n) {
   uint8_t* cb = (uint8_t*)st->carry;
   for (int64_t p = threadIdx.x; p < n; p += blockDim.x) cb[t + p] = piece[p];
 }
 
-// Digest, one wave: lane l forms words 2l and 2l + 1 of the padded open block
-// (t carried bytes, a byte 0x01, zeros), then the climb. nodes[j] is the
-// number of level-j nodes of the whole string (level 1: blocks).
+// Digest: the pending tree step (all threads), then one wave: lane l forms
+// words 2l and 2l + 1 of the padded open block (t carried bytes, a byte 0x01,
+// zeros), then the climb. nodes[j] is the number of level-j nodes of the
+// whole string (level 1: blocks).
 struct Nodes {
   uint64_t n[LMAX + 1];
 };
 template <bool WIDE>
-__global__ void incr_digest(const IncrState* st, uint32_t t, Nodes N, const void* keysv, void* out, uint32_t flags) {
+__global__ __launch_bounds__(256) void incr_digest(IncrState* st, uint32_t t, Nodes N, const void* keysv, void* out,
+                                                   uint32_t flags, uint32_t pending, IncrTree prev) {
   using T = Tr<WIDE>;
   using S = typename T::Sum;
   using K = typename T::key_t;
+  __shared__ uint64_t pend[3];
   const K* keys = (const K*)keysv;
+  if (pending) tree_step<WIDE>(st, keys, prev, pend);  // the last append's levels >= 2
+  if (threadIdx.x >= 64) return;
   const int lane = (int)threadIdx.x;
   S s;
   zero(s);
@@ -393,13 +406,14 @@ __global__ void incr_reset(IncrState* st) {
 }  // namespace
 
 hipError_t launch_incr_append(int wide, const IncrArgs& a, hipStream_t s) {
-  if (wide) {
-    hipLaunchKernelGGL(incr_blocks<true>, dim3(a.nwg), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(incr_tree<true>, dim3(1), dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL(incr_blocks<false>, dim3(a.nwg), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(incr_tree<false>, dim3(1), dim3(256), 0, s, a);
-  }
+  if (wide) hipLaunchKernelGGL(incr_blocks<true>, dim3(a.nwg), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(incr_blocks<false>, dim3(a.nwg), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_incr_flush(int wide, IncrState* st, const void* keys, const IncrTree& t, hipStream_t s) {
+  if (wide) hipLaunchKernelGGL(incr_flush<true>, dim3(1), dim3(256), 0, s, st, keys, t);
+  else hipLaunchKernelGGL(incr_flush<false>, dim3(1), dim3(256), 0, s, st, keys, t);
   return hipGetLastError();
 }
 
@@ -408,12 +422,14 @@ hipError_t launch_incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, in
   return hipGetLastError();
 }
 
-hipError_t launch_incr_digest(int wide, const IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
-                              void* out, uint32_t flags, hipStream_t s) {
+hipError_t launch_incr_digest(int wide, IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
+                              void* out, uint32_t flags, uint32_t pending, const IncrTree& prev, hipStream_t s) {
   Nodes N;
   for (int j = 0; j <= LMAX; ++j) N.n[j] = nodes[j];
-  if (wide) hipLaunchKernelGGL(incr_digest<true>, dim3(1), dim3(64), 0, s, st, t, N, keys, out, flags);
-  else hipLaunchKernelGGL(incr_digest<false>, dim3(1), dim3(64), 0, s, st, t, N, keys, out, flags);
+  if (wide)
+    hipLaunchKernelGGL(incr_digest<true>, dim3(1), dim3(256), 0, s, st, t, N, keys, out, flags, pending, prev);
+  else
+    hipLaunchKernelGGL(incr_digest<false>, dim3(1), dim3(256), 0, s, st, t, N, keys, out, flags, pending, prev);
   return hipGetLastError();
 }
 

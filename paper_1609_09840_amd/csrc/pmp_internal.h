@@ -24,8 +24,9 @@ hipError_t launch_plain_string(int wide, const uint8_t* buf, uint64_t buf_bytes,
                                uint64_t scratch_slots, hipStream_t s);
 hipError_t launch_incr_append(int wide, const IncrArgs& a, hipStream_t s);
 hipError_t launch_incr_carry(IncrState* st, uint32_t t, const uint8_t* piece, int64_t n, hipStream_t s);
-hipError_t launch_incr_digest(int wide, const IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
-                              void* out, uint32_t flags, hipStream_t s);
+hipError_t launch_incr_flush(int wide, IncrState* st, const void* keys, const IncrTree& t, hipStream_t s);
+hipError_t launch_incr_digest(int wide, IncrState* st, uint32_t t, const uint64_t* nodes, const void* keys,
+                              void* out, uint32_t flags, uint32_t pending, const IncrTree& prev, hipStream_t s);
 hipError_t launch_incr_reset(IncrState* st, hipStream_t s);
 // exclusive scan of m uint32 counts into start[0..m] (start[m] = total);
 // bsum: excl_scan_work_bytes(m) bytes of device scratch
