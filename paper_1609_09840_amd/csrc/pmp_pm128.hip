@@ -15,9 +15,9 @@
 // Launches: (1) the number of units of each string of more than one block
 // (a unit is a quarter of a level-2 node: 32 blocks) and an exclusive scan
 // of those counts; (2) strings of one block, four lanes each; (3) one wave
-// per unit: lane l forms words 2l and 2l + 1 of each of the unit's blocks,
-// the block's exact sum is reduced over the wave and folded, and the unit's
-// share of its node, sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
+// per unit, 8 lanes per block and 8 blocks at a time: each block's exact sum
+// is reduced over its 8 lanes and folded, and the unit's share of its node,
+// sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
 // per string of more than one block adds each node's quarters and b_2 and
 // climbs the levels above 2 in place.
 #include "pmp_device.hpp"
@@ -235,7 +235,14 @@ __device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
   return lo;
 }
 
-// Unit g: quarter k of string s's level-2 nodes (blocks QB k ..).
+// Unit g: quarter k of string s's level-2 nodes (blocks QB k ..). The wave
+// takes 8 blocks at a time, 8 lanes per block: lane j of a group sums words
+// j, j + 8, ..., j + 120 of its block (16-byte loads, 128 contiguous bytes
+// per group and instruction), the group adds its eight sums (three steps),
+// folds, and multiplies by the block's level-2 key. A block of data words
+// only is read with plain loads of the aligned dwords holding each word (the
+// one past it only when misaligned); the string's last block is padded and
+// read with guarded loads.
 __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
   const int64_t s = unit_string(A, g, lane);
   const int64_t k = g - A.start[s];
@@ -244,63 +251,60 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
   const uint8_t* blo = A.buf;
   const uint8_t* bhi = A.buf + A.buf_bytes;
   const int64_t n1 = blocks_of(len);
-
-  uint64_t ka[4];  // level-1 keys of words 2 lane, 2 lane + 1
-  key_a(A.keys, 1, 2 * lane, &ka[0], &ka[1]);
-  key_a(A.keys, 1, 2 * lane + 1, &ka[2], &ka[3]);
-
-  // A block of data words only (every block but the string's last) is read
-  // with plain loads: lane l's 32 bytes at 32 l, from the aligned dwords
-  // holding them (the one past them only when misaligned: it then holds
-  // their last bytes). The next block's loads are issued before this
-  // block's arithmetic.
+  const int grp = lane / 8, j = lane % 8;
   const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
-  auto issue = [&](int64_t c, uint32_t* d) -> bool {
-    if (c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES > len) return false;
-    const uint64_t a4 = (uint64_t)(uintptr_t)(str + c * BLK_BYTES + 32 * lane) - sh;
-    const Q q0 = load16(gp16(a4)), q1 = load16(gp16(a4 + 16));
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      d[u] = q0.d[u];
-      d[4 + u] = q1.d[u];
-    }
-    d[8] = sh ? *(const uint32_t*)gp16(a4 + 32) : 0u;
-    return true;
-  };
-  A5 node;
+
+  A5 node;  // this group's blocks' share of the node
   zero(node);
   const int64_t c0 = k * QB;
   const int64_t c1 = c0 + QB < n1 ? c0 + QB : n1;
-  uint32_t dc[9], dn[9];
-  bool fc = issue(c0, dc);
-  for (int64_t c = c0; c < c1; ++c) {
-    const bool fn = c + 1 < c1 && issue(c + 1, dn);
-    uint64_t x0, x1, y0, y1;
-    if (fc) {
-      uint32_t x[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = align_bytes(dc[u + 1], dc[u], sh);
-      x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
-      x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
-      y0 = (uint64_t)x[4] | ((uint64_t)x[5] << 32);
-      y1 = (uint64_t)x[6] | ((uint64_t)x[7] << 32);
-    } else {  // the string's last block: padded, guarded reads
-      word128(str, len, c * BLOCK + 2 * lane, blo, bhi, &x0, &x1);
-      word128(str, len, c * BLOCK + 2 * lane + 1, blo, bhi, &y0, &y1);
-    }
+  for (int64_t cb = c0; cb < c1; cb += 8) {
+    const int64_t c = cb + grp;
     A5 sum;
     zero(sum);
-    mac(sum, ka[0], ka[1], x0, x1);
-    mac(sum, ka[2], ka[3], y0, y1);
-    wave_sum(sum);
-    add_b(sum, A.keys, 1);
-    const F128 z1 = fold(sum);
-    uint64_t a0, a1;
-    key_a(A.keys, 2, (uint32_t)(c % BLOCK), &a0, &a1);
-    mac_fe(node, a0, a1, z1);
+    if (c < c1) {
+      const bool full = c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES <= len;
+#pragma unroll 4
+      for (int t = 0; t < 16; ++t) {
+        const int64_t w = c * BLOCK + j + 8 * t;
+        uint64_t x0, x1, a0, a1;
+        if (full) {
+          const uint64_t a4 = (uint64_t)(uintptr_t)(str + W16 * w) - sh;
+          const Q q = load16(gp16(a4));
+          const uint32_t d4 = sh ? *(const uint32_t*)gp16(a4 + 16) : 0u;
+          const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], d4};
+          uint32_t x[4];
 #pragma unroll
-    for (int u = 0; u < 9; ++u) dc[u] = dn[u];
-    fc = fn;
+          for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
+          x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+          x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+        } else {
+          word128(str, len, w, blo, bhi, &x0, &x1);
+        }
+        key_a(A.keys, 1, (uint32_t)(j + 8 * t), &a0, &a1);
+        mac(sum, a0, a1, x0, x1);
+      }
+    }
+    for (int m = 1; m < 8; m <<= 1) {  // the block's sum in every lane of the group
+      A5 o;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) o.w[i] = shx64(sum.w[i], m);
+      add(sum, o);
+    }
+    if (c < c1 && j == 0) {
+      add_b(sum, A.keys, 1);
+      const F128 z1 = fold(sum);
+      uint64_t a0, a1;
+      key_a(A.keys, 2, (uint32_t)(c % BLOCK), &a0, &a1);
+      mac_fe(node, a0, a1, z1);
+    }
+  }
+  // the eight groups' shares (held by lanes 0, 8, ..., 56; zero elsewhere)
+  for (int m = 8; m < 64; m <<= 1) {
+    A5 o;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) o.w[i] = shx64(node.w[i], m);
+    add(node, o);
   }
   // the quarter's share of its node, reduced (b_2 is added with the node)
   if (lane == 0 && (uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = fold(node);
