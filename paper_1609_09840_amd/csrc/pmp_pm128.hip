@@ -18,7 +18,7 @@
 // per unit, 8 lanes per block and 8 blocks at a time: each block's exact sum
 // is reduced over its 8 lanes and folded, and the unit's share of its node,
 // sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
-// per string of more than one block adds each node's quarters and b_2 and
+// per string of more than one block adds each node's units and b_2 and
 // climbs the levels above 2 in place.
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
@@ -31,6 +31,7 @@ constexpr uint64_t K128 = 51;
 constexpr int W16 = 16;                      // bytes per word
 constexpr uint64_t BLK_BYTES = BLOCK * W16;  // 2 KiB per level-1 block
 constexpr int QB = 32;                       // blocks per unit: a quarter of a level-2 node
+constexpr int UPN = BLOCK / QB;              // units per level-2 node
 
 struct A5 {
   uint64_t w[5];
@@ -175,7 +176,7 @@ __device__ __forceinline__ void word128(const uint8_t* s, int64_t len, int64_t w
 }
 
 __device__ __forceinline__ int64_t blocks_of(int64_t len) { return (len / W16 + 1 + BLOCK - 1) / BLOCK; }
-// units of the node kernel: quarters of level-2 nodes (QB blocks); strings
+// units of the node kernel: parts of level-2 nodes (QB blocks); strings
 // of one block have none (the short-string kernel takes them)
 __device__ __forceinline__ int64_t units_of(int64_t len) {
   const int64_t n1 = blocks_of(len);
@@ -235,7 +236,7 @@ __device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
   return lo;
 }
 
-// Unit g: quarter k of string s's level-2 nodes (blocks QB k ..). The wave
+// Unit g: part k of string s's level-2 nodes (blocks QB k ..). The wave
 // takes 8 blocks at a time, 8 lanes per block: lane j of a group sums words
 // j, j + 8, ..., j + 120 of its block (16-byte loads, 128 contiguous bytes
 // per group and instruction), the group adds its eight sums (three steps),
@@ -264,7 +265,7 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
     zero(sum);
     if (c < c1) {
       const bool full = c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES <= len;
-#pragma unroll 4
+#pragma unroll 2
       for (int t = 0; t < 16; ++t) {
         const int64_t w = c * BLOCK + j + 8 * t;
         uint64_t x0, x1, a0, a1;
@@ -306,7 +307,7 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
     for (int i = 0; i < 5; ++i) o.w[i] = shx64(node.w[i], m);
     add(node, o);
   }
-  // the quarter's share of its node, reduced (b_2 is added with the node)
+  // the unit's share of its node, reduced (b_2 is added with the node)
   if (lane == 0 && (uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = fold(node);
 }
 
@@ -375,7 +376,7 @@ __device__ __forceinline__ void add_fe(A5& s, const F128& z) {
 }
 
 // A string of more than one block, by one wave: its level-2 nodes from their
-// quarters (node k = the sum of quarters 4k .. 4k + 3 plus b_2), then levels
+// units (node k = the sum of units UPN k .. UPN k + UPN - 1 plus b_2), then levels
 // 3 and up. Each step writes its values over the previous ones: value q goes
 // to index q, at or below its first input; a wave's loads of a step are done
 // before its stores, and steps are ordered by a fence.
@@ -383,7 +384,7 @@ __device__ void climb_string(const P128Args& A, int64_t s, int lane) {
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const int64_t n1 = blocks_of(len);
   if (n1 == 1) return;
-  const int64_t nq = (n1 + QB - 1) / QB;  // quarter values
+  const int64_t nq = (n1 + QB - 1) / QB;  // unit values
   if ((uint64_t)(A.start[s] + nq) > A.zcap) return;
   F128* v = A.z2 + A.start[s];
   int64_t n = (n1 + BLOCK - 1) / BLOCK;  // level-2 values
@@ -392,10 +393,10 @@ __device__ void climb_string(const P128Args& A, int64_t s, int lane) {
     A5 sum;
     zero(sum);
     if (k < n) {
-      for (int64_t u = 4 * k; u < 4 * k + 4 && u < nq; ++u) add_fe(sum, v[u]);
+      for (int64_t u = UPN * k; u < UPN * k + UPN && u < nq; ++u) add_fe(sum, v[u]);
       add_b(sum, A.keys, 2);
     }
-    __threadfence();  // every lane has read its quarters
+    __threadfence();  // every lane has read its units
     if (k < n) v[k] = fold(sum);
     __threadfence();
   }
