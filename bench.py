@@ -9,7 +9,9 @@ c1 | c2 | c3 (see paper_1609_09840_amd/workloads.py).
 
 Prints ONE JSON line. Besides the headline value it carries:
   roofline      algorithmic bytes per launch / mean launch time (HIP events
-                on the launch stream) against the 8 TB/s HBM peak; `traffic`
+                on the launch stream) against the 8 TB/s HBM peak, and
+                against the read rate a plain streaming kernel reaches on
+                the same device (frac_of_achievable); `traffic`
                 is the measured HBM bytes per launch from the committed
                 rocprofv3 counter summary when it was taken on the current
                 kernel source, else null;
@@ -122,6 +124,24 @@ def cpu_model() -> str:
 PAPER_CONTEXT = {"hardware": "Intel Core i7-4770 (Haswell), one core at 3.4 GHz, AVX2",
                  "pm32_bytes_per_cycle": 4.7, "pm64_bytes_per_cycle": 3.3,
                  "pm32_GBps": 16.0, "pm64_GBps": 11.2}
+
+
+_READ_BW = {}
+
+
+def achievable_read_gbs(dev) -> float:
+    """GB/s a plain streaming read kernel reaches over 1 GiB of device memory
+    (pmp_probe_read_bw), measured once per run: the achievable HBM read rate
+    the kernels are compared with beside the published 8 TB/s."""
+    if "v" not in _READ_BW:
+        import torch
+
+        from paper_1609_09840_amd import pmp
+
+        buf = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        _READ_BW["v"] = pmp.pmp_probe_read_bw(buf) / 1e9
+        del buf
+    return _READ_BW["v"]
 
 
 def mul_roofline(wl, launch_ms: float) -> dict:
@@ -325,7 +345,9 @@ def incremental(dev, total: int = 1 << 30, pieces=(1 << 20, 16 << 20, 256 << 20)
                        "achieved": best["append_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(best["append_GBps"] / HBM_PEAK_GBS, 4),
                        "traffic": read_traffic("256mib_" + ("pm64" if best["variant"] == "PM+64" else "pm32"),
-                                               "incr_blocks", "pmp_incr.hip")}
+                                               "incr_blocks", "pmp_incr.hip"),
+                       "achievable_read_GBps": round(achievable_read_gbs(dev), 1),
+                       "frac_of_achievable": round(best["append_GBps"] / achievable_read_gbs(dev), 4)}
     return res
 
 
@@ -677,6 +699,8 @@ def main():
             "kernel": KERNEL,
             "algorithmic_bytes_per_launch": alg,
             "mean_launch_ms": round(launch_ms, 5),
+            "achievable_read_GBps": round(achievable_read_gbs(dev), 1),
+            "frac_of_achievable": round(achieved / achievable_read_gbs(dev), 4),
         },
         "mul_roofline": mul_roofline(wl, launch_ms),
         "paper_context": PAPER_CONTEXT,

@@ -412,6 +412,14 @@ int pmp_debug_fold(int wide, const void* d_w0, const void* d_w1, const uint32_t*
  * synchronous (about a millisecond). */
 int pmp_probe_mad_rate(double* mads_per_s);
 
+/* Measurement hook (not on the path): the read bandwidth of a plain
+ * streaming kernel (workgroups take 32 KiB chunks in turn, 16-byte loads,
+ * eight in flight per thread) over `bytes` of device memory at d_buf
+ * (at least 1 MiB, 16-byte aligned), in bytes per second: the achievable
+ * HBM read rate the kernels are compared with beside the published peak.
+ * Allocates and frees a small buffer and a stream; synchronous. */
+int pmp_probe_read_bw(const void* d_buf, uint64_t bytes, double* bytes_per_s);
+
 /* Message for the last error on this thread (never NULL). */
 const char* pmp_last_error(void);
 /* Library version string. */

@@ -57,6 +57,8 @@ int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 namespace pmp {
 // the multiply-rate probe (pmp_probe.hip): `blocks` blocks of 256 threads
 hipError_t launch_mad_probe(uint64_t* out, int blocks, uint32_t iters, hipStream_t s);
+// the read-bandwidth probe: n16 pieces of 16 bytes
+hipError_t launch_read_probe(const void* buf, uint64_t n16, uint32_t* out, int blocks, hipStream_t s);
 }  // namespace pmp
 
 struct pmp_plan {
@@ -705,6 +707,43 @@ int pmp_probe_mad_rate(double* mads_per_s) {
   if (e != hipSuccess) return hip_fail(e, "mad probe");
   if (ms <= 0) return fail(PMP_E_HIP, "mad probe took no time");
   *mads_per_s = 3.0 * blocks * 256.0 * iters * 8.0 / (ms * 1e-3);
+  return PMP_OK;
+}
+
+int pmp_probe_read_bw(const void* d_buf, uint64_t bytes, double* bytes_per_s) {
+  if (!bytes_per_s || !d_buf) return fail(PMP_E_INVALID_ARG, "NULL argument");
+  *bytes_per_s = 0;
+  if (bytes < (1u << 20) || ((uintptr_t)d_buf & 15u)) return fail(PMP_E_INVALID_ARG, "need >= 1 MiB, 16-byte aligned");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "device properties");
+  const int blocks = prop.multiProcessorCount * 16;  // 16 waves per SIMD's worth of lanes
+  const uint64_t n16 = bytes / 16;
+  uint32_t* out = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipMalloc(&out, (size_t)blocks * 256 * sizeof(uint32_t));
+  if (e != hipSuccess) return fail(PMP_E_NOMEM, "probe buffer: %s", hipGetErrorString(e));
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float ms = 0;
+  const int reps = 5;
+  if (e == hipSuccess) e = pmp::launch_read_probe(d_buf, n16, out, blocks, s);  // warm
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = pmp::launch_read_probe(d_buf, n16, out, blocks, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(out);
+  if (e != hipSuccess) return hip_fail(e, "read probe");
+  if (ms <= 0) return fail(PMP_E_HIP, "read probe took no time");
+  *bytes_per_s = (double)reps * (double)(n16 * 16) / (ms * 1e-3);
   return PMP_OK;
 }
 

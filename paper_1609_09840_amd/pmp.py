@@ -122,6 +122,7 @@ def _load():
         "pmp_plan_set_tile": [vp, i32, i32],
         "pmp_plan_tune": [vp, i32, u32, u64, i32],
         "pmp_probe_mad_rate": [ctypes.POINTER(ctypes.c_double)],
+        "pmp_probe_read_bw": [vp, u64, ctypes.POINTER(ctypes.c_double)],
         "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
@@ -609,6 +610,14 @@ def pmp_hash_plain(wide: bool, buf, h_offsets: np.ndarray, keys, out, flags: int
                                _dev_ptr(scratch, "scratch"), scratch.numel() * scratch.element_size(),
                                _stream(stream)))
     return out
+
+
+def pmp_probe_read_bw(buf) -> float:
+    """Bytes per second a plain streaming read kernel reaches over the device
+    tensor `buf` (at least 1 MiB)."""
+    r = ctypes.c_double()
+    _check(_lib.pmp_probe_read_bw(_dev_ptr(buf, "buf"), buf.numel() * buf.element_size(), ctypes.byref(r)))
+    return r.value
 
 
 def pmp_probe_mad_rate() -> float:
