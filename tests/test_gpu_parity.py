@@ -326,3 +326,18 @@ def test_mad_probe_rate():
     say("case mad probe")
     r = pmp.pmp_probe_mad_rate()
     assert 1e12 < r < 1e15, r
+
+
+def test_read_probe_rate():
+    """The read-bandwidth probe returns a plausible rate for 256 MiB (between
+    0.5 and 20 TB/s) and refuses a buffer under 1 MiB."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    say("case read probe")
+    b = torch.ones(256 << 20, dtype=torch.uint8, device=U.dev())
+    r = pmp.pmp_probe_read_bw(b)
+    assert 5e11 < r < 2e13, r
+    with pytest.raises(pmp.PmpError):
+        pmp.pmp_probe_read_bw(b[: 1 << 19])
