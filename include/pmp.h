@@ -317,25 +317,33 @@ int pmp_hash128(const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offse
  * of pmp_hash32/64 with the batch's flags (PMP_OUT_FIELD is refused).
  *
  * pmp_table_build: hashes the batch `keys` (key i = its string i) into
- * keys->out (count outputs; keep them: probes compare full hashes), then
- * builds a CSR table in caller-owned device arrays: d_bucket_start[M + 1]
- * (int64; bucket b holds entries [start[b], start[b + 1])) and
- * d_entries[count] (int64 key indices). The order of the entries within a
- * bucket is unspecified. d_work: device scratch of at least
+ * keys->out (count outputs), then builds a CSR table in caller-owned device
+ * arrays: d_bucket_start[M + 1] (int64; bucket b holds entries
+ * [start[b], start[b + 1])) and d_entries[count], one 32-byte record per key
+ * (its index, its n-bit hash, its offset and length in keys->buf). The
+ * order of the entries within a bucket is unspecified. d_work: device
+ * scratch of at least
  * pmp_table_work_bytes(M) bytes. M = nbuckets in [1, 2^31]. Asynchronous on
  * `stream`; plan as for the hash calls.
  *
  * pmp_table_probe: hashes the batch `queries` into queries->out, then writes
  * d_result[q] = the smallest key index i whose bytes equal query q's, or -1.
- * `keys` is the batch given to the build (buf, offsets and out = its hashes
- * are read); queries and keys must share wide, the key table pointer and the
+ * `keys` is the batch given to the build (its buf is read; the entries hold
+ * the rest); queries and keys must share wide, the key table pointer and the
  * flags. Returns PMP_E_INVALID_ARG on NULL pointers, mismatched batches or M
  * out of range. */
+typedef struct pmp_table_entry {
+  int64_t key;     /* key index in the build's batch */
+  uint64_t hash;   /* its n-bit output (PM+32: zero-extended) */
+  int64_t offset;  /* its first byte in the build's buf */
+  int64_t length;  /* its length in bytes */
+} pmp_table_entry;
 uint64_t pmp_table_work_bytes(uint64_t nbuckets);
 int pmp_table_build(pmp_plan* plan, const pmp_batch* keys, uint64_t nbuckets, int64_t* d_bucket_start,
-                    int64_t* d_entries, void* d_work, uint64_t work_bytes, pmp_stream_t stream);
+                    pmp_table_entry* d_entries, void* d_work, uint64_t work_bytes, pmp_stream_t stream);
 int pmp_table_probe(pmp_plan* plan, const pmp_batch* queries, const pmp_batch* keys, uint64_t nbuckets,
-                    const int64_t* d_bucket_start, const int64_t* d_entries, int64_t* d_result, pmp_stream_t stream);
+                    const int64_t* d_bucket_start, const pmp_table_entry* d_entries, int64_t* d_result,
+                    pmp_stream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* Incremental hashing of ONE string delivered in pieces (Sec. 4: with its

@@ -802,7 +802,7 @@ int pmp_hash128(const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offse
 uint64_t pmp_table_work_bytes(uint64_t nbuckets) { return pmp::table_work_bytes(nbuckets); }
 
 int pmp_table_build(pmp_plan* plan, const pmp_batch* keys, uint64_t nbuckets, int64_t* d_bucket_start,
-                    int64_t* d_entries, void* d_work, uint64_t work_bytes, pmp_stream_t stream) {
+                    pmp_table_entry* d_entries, void* d_work, uint64_t work_bytes, pmp_stream_t stream) {
   if (!keys || !d_bucket_start || !d_work || (keys->count > 0 && !d_entries))
     return fail(PMP_E_INVALID_ARG, "NULL argument");
   int r = check_batch(keys);
@@ -816,14 +816,15 @@ int pmp_table_build(pmp_plan* plan, const pmp_batch* keys, uint64_t nbuckets, in
     r = run_two(plan, keys, nullptr, (hipStream_t)stream);
     if (r) return r;
   }
-  hipError_t e = pmp::launch_table_build(keys->out, keys->wide, keys->count, nbuckets, d_bucket_start, d_entries,
-                                         d_work, (hipStream_t)stream);
+  hipError_t e = pmp::launch_table_build(keys->out, keys->wide, keys->count, nbuckets, keys->offsets,
+                                         d_bucket_start, d_entries, d_work, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "table build launch");
   return PMP_OK;
 }
 
 int pmp_table_probe(pmp_plan* plan, const pmp_batch* queries, const pmp_batch* keys, uint64_t nbuckets,
-                    const int64_t* d_bucket_start, const int64_t* d_entries, int64_t* d_result, pmp_stream_t stream) {
+                    const int64_t* d_bucket_start, const pmp_table_entry* d_entries, int64_t* d_result,
+                    pmp_stream_t stream) {
   if (!queries || !keys || !d_bucket_start || (queries->count > 0 && !d_result))
     return fail(PMP_E_INVALID_ARG, "NULL argument");
   int r = check_batch(queries);
@@ -838,8 +839,8 @@ int pmp_table_probe(pmp_plan* plan, const pmp_batch* queries, const pmp_batch* k
   r = run_two(plan, queries, nullptr, (hipStream_t)stream);
   if (r) return r;
   hipError_t e = pmp::launch_table_probe(queries->buf, queries->offsets, queries->count, queries->out, keys->buf,
-                                         keys->offsets, keys->out, keys->wide, nbuckets, d_bucket_start, d_entries,
-                                         d_result, (hipStream_t)stream);
+                                         keys->wide, nbuckets, d_bucket_start, d_entries, d_result,
+                                         (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "table probe launch");
   return PMP_OK;
 }

@@ -33,11 +33,11 @@ hipError_t launch_incr_reset(IncrState* st, hipStream_t s);
 uint64_t excl_scan_work_bytes(uint64_t m);
 hipError_t launch_excl_scan_u32(const uint32_t* cnt, uint64_t m, int64_t* start, uint64_t* bsum, hipStream_t s);
 uint64_t table_work_bytes(uint64_t m);
-hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, int64_t* start, int64_t* entries,
-                              void* work, hipStream_t s);
+hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, const int64_t* koff,
+                              int64_t* start, pmp_table_entry* entries, void* work, hipStream_t s);
 hipError_t launch_table_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
-                              const int64_t* koff, const void* kh, uint32_t wide, uint64_t m, const int64_t* start,
-                              const int64_t* entries, int64_t* result, hipStream_t s);
+                              uint32_t wide, uint64_t m, const int64_t* start, const pmp_table_entry* entries,
+                              int64_t* result, hipStream_t s);
 uint64_t pm128_scratch_bytes(int64_t count, uint64_t buf_bytes);
 hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* offsets, int64_t count,
                         const uint64_t* keys, void* out, uint32_t flags, void* scratch, hipStream_t s);

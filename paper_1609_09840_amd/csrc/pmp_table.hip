@@ -4,13 +4,18 @@
 //
 // Build (after the keys are hashed by the batch kernel): count the keys of
 // each bucket with atomics, an exclusive scan of the counts gives the CSR
-// bucket starts, and a scatter with per-bucket atomic cursors places each key
-// index in its bucket. The order inside a bucket is whatever the atomics
-// give; the probe does not depend on it.
+// bucket starts, and a scatter with per-bucket atomic cursors places each
+// key's record in its bucket. The order inside a bucket is whatever the
+// atomics give; the probe does not depend on it.
 //
-// Probe (after the queries are hashed): one lane per query walks its bucket,
-// skips keys whose full n-bit hash or length differs, compares the bytes of
-// the rest and keeps the smallest equal key index (or -1).
+// Each entry is a 32-byte record (key index, hash, offset, length), so that
+// a probe reads one record per candidate.
+//
+// Probe (after the queries are hashed): one lane per query walks its bucket
+// for the smallest key with the query's full n-bit hash and length, then
+// compares that key's bytes once (all lanes of a wave together, after the
+// walk); only when a full-hash collision has different bytes does the lane
+// compare every such key. The result is the smallest equal key index, or -1.
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
 
@@ -99,11 +104,21 @@ __global__ void tab_scan_add(int64_t* start, uint64_t m, const uint64_t* bsum) {
     if (base + k < m) start[base + k] += add;
 }
 
-__global__ void tab_scatter(const void* h, uint32_t wide, int64_t n, uint64_t m, const int64_t* start, uint32_t* fill,
-                            int64_t* entries) {
+// Each key's record (index, hash, offset, length) goes to its bucket: a
+// probe then reads one 32-byte record per candidate instead of the entry,
+// the key's hash and its offsets from three places.
+__global__ void tab_scatter(const void* h, uint32_t wide, int64_t n, uint64_t m, const int64_t* koff,
+                            const int64_t* start, uint32_t* fill, pmp_table_entry* entries) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t b = hash_at(h, wide, i) % m;
-    entries[start[b] + atomicAdd(fill + b, 1u)] = i;
+    const uint64_t hi = hash_at(h, wide, i);
+    const int64_t o0 = koff[i], o1 = koff[i + 1];
+    const uint64_t b = hi % m;
+    pmp_table_entry r;
+    r.key = i;
+    r.hash = hi;
+    r.offset = o0;
+    r.length = o1 - o0;
+    entries[start[b] + atomicAdd(fill + b, 1u)] = r;
   }
 }
 
@@ -156,19 +171,32 @@ __device__ bool bytes_equal(const uint8_t* a, const uint8_t* b, int64_t len) {
 }
 
 __global__ void tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
-                          const int64_t* koff, const void* kh, uint32_t wide, uint64_t m, const int64_t* start,
-                          const int64_t* entries, int64_t* result) {
+                          uint32_t wide, uint64_t m, const int64_t* start, const pmp_table_entry* entries,
+                          int64_t* result) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q0 = qoff[q], len = qoff[q + 1] - q0;
     const uint64_t hq = hash_at(qh, wide, q);
     const uint64_t b = hq % m;
-    int64_t best = -1;
-    for (int64_t e = start[b], e1 = start[b + 1]; e < e1; ++e) {
-      const int64_t i = entries[e];
-      if ((best >= 0 && i > best) || hash_at(kh, wide, i) != hq) continue;
-      const int64_t k0 = koff[i];
-      if (koff[i + 1] - k0 != len) continue;
-      if (bytes_equal(qbuf + q0, kbuf + k0, len)) best = i;
+    const int64_t e0 = start[b], e1 = start[b + 1];
+    // the smallest key with the query's hash and length; the answer if its
+    // bytes are equal (every equal key has that hash and length)
+    int64_t cand = -1, coff = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const pmp_table_entry r = entries[e];
+      if (r.hash == hq && r.length == len && (cand < 0 || r.key < cand)) {
+        cand = r.key;
+        coff = r.offset;
+      }
+    }
+    int64_t best = cand;
+    if (cand >= 0 && !bytes_equal(qbuf + q0, kbuf + coff, len)) {
+      // a full-hash collision with different bytes: compare every candidate
+      best = -1;
+      for (int64_t e = e0; e < e1; ++e) {
+        const pmp_table_entry r = entries[e];
+        if (r.hash != hq || r.length != len || r.key == cand || (best >= 0 && r.key > best)) continue;
+        if (bytes_equal(qbuf + q0, kbuf + r.offset, len)) best = r.key;
+      }
     }
     result[q] = best;
   }
@@ -196,8 +224,8 @@ hipError_t launch_excl_scan_u32(const uint32_t* cnt, uint64_t m, int64_t* start,
   return hipGetLastError();
 }
 
-hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, int64_t* start, int64_t* entries,
-                              void* work, hipStream_t s) {
+hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, const int64_t* koff,
+                              int64_t* start, pmp_table_entry* entries, void* work, hipStream_t s) {
   uint32_t* cnt = (uint32_t*)work;
   uint64_t* bsum = (uint64_t*)((char*)work + ((4 * m + 7) & ~7ull));
   hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
@@ -206,17 +234,17 @@ hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t 
   if (e != hipSuccess) return e;
   if (n > 0) {
     hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
-    hipLaunchKernelGGL(tab_scatter, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, start, cnt, entries);
+    hipLaunchKernelGGL(tab_scatter, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, koff, start, cnt, entries);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_table_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
-                              const int64_t* koff, const void* kh, uint32_t wide, uint64_t m, const int64_t* start,
-                              const int64_t* entries, int64_t* result, hipStream_t s) {
+                              uint32_t wide, uint64_t m, const int64_t* start, const pmp_table_entry* entries,
+                              int64_t* result, hipStream_t s) {
   if (nq > 0)
-    hipLaunchKernelGGL(tab_probe, dim3(grid_for(nq)), dim3(256), 0, s, qbuf, qoff, nq, qh, kbuf, koff, kh, wide, m,
-                       start, entries, result);
+    hipLaunchKernelGGL(tab_probe, dim3(grid_for(nq)), dim3(256), 0, s, qbuf, qoff, nq, qh, kbuf, wide, m, start,
+                       entries, result);
   return hipGetLastError();
 }
 

@@ -491,7 +491,8 @@ class Table:
         self.hashes = _out_for(wide, count, flags, dev)
         self.batch = make_batch(wide, buf, offsets, keys, self.hashes, flags)
         self.bucket_start = torch.empty(self.nbuckets + 1, dtype=torch.int64, device=dev)
-        self.entries = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+        # one record per key: index, hash, offset, length (int64 each)
+        self.entries = torch.empty((max(count, 1), 4), dtype=torch.int64, device=dev)
         nw = int(_lib.pmp_table_work_bytes(self.nbuckets))
         self.work = torch.empty(max(nw, 8), dtype=torch.uint8, device=dev)
         _check(_lib.pmp_table_build(_plan_ptr(plan), ctypes.byref(self.batch), self.nbuckets,

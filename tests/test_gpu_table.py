@@ -1,8 +1,9 @@
 """Hash table of variable-length keys (pmp_table_*) against the oracle.
 
 bucket_start must equal the oracle's exactly; each bucket must hold the same
-key indices as the oracle's (the order inside a bucket is unspecified); every
-probe result must equal the oracle's (smallest equal key, or -1). Expected
+key indices as the oracle's (the order inside a bucket is unspecified), each
+entry's record the key's hash, offset and length; every probe result must
+equal the oracle's (smallest equal key, or -1). Expected
 values come from oracle/ only; inputs from the seeded generators."""
 from __future__ import annotations
 
@@ -63,6 +64,19 @@ def check_table(wide, kbuf, koff, kh, m, start, entries):
     assert np.array_equal(entries[:n][np.argsort(key, kind="stable")], want_entries)
 
 
+def entry_keys(t, koff, kh):
+    """The key index of each entry, after checking the rest of its record
+    (hash, offset, length) against the oracle's hashes and the offsets."""
+    rec = t.entries.cpu().numpy()
+    n = len(koff) - 1
+    keys = rec[:n, 0]
+    if n:
+        assert np.array_equal(rec[:n, 1].view(np.uint64), kh[keys])
+        assert np.array_equal(rec[:n, 2], koff[keys])
+        assert np.array_equal(rec[:n, 3], np.diff(koff)[keys])
+    return keys
+
+
 def run(wide, kparts, qparts, m, flags, keys_seed):
     import torch
 
@@ -78,11 +92,11 @@ def run(wide, kparts, qparts, m, flags, keys_seed):
     res = t.probe(dq, dqo)
     torch.cuda.synchronize()
     start = t.bucket_start.cpu().numpy()
-    entries = t.entries.cpu().numpy()
     got = res.cpu().numpy()
     kh = oracle_hashes(wide, kbuf, koff, keys_np, flags)
     qh = oracle_hashes(wide, qbuf, qoff, keys_np, flags)
     assert np.array_equal(U.as_u64(t.hashes.cpu().numpy()), kh)
+    entries = entry_keys(t, koff, kh)
     return kbuf, koff, kh, qbuf, qoff, qh, start, entries, got
 
 
@@ -140,7 +154,7 @@ def test_table_c2_full():
     torch.cuda.synchronize()
     kh = U.oracle_hash(rg, keys_np)
     assert np.array_equal(U.as_u64(t.hashes.cpu().numpy()), kh)
-    check_table(False, rg.buf, rg.offsets, kh, m, t.bucket_start.cpu().numpy(), t.entries.cpu().numpy())
+    check_table(False, rg.buf, rg.offsets, kh, m, t.bucket_start.cpu().numpy(), entry_keys(t, rg.offsets, kh))
     got = res.cpu().numpy()
     qh = U.oracle_hash(W.Ragged(qbuf, qoff, False), keys_np)
     want_start, want_entries = T.build(kh, m)
@@ -171,3 +185,37 @@ def test_table_no_keys():
     torch.cuda.synchronize()
     assert np.array_equal(t.bucket_start.cpu().numpy(), np.zeros(17, np.int64))
     assert (res.cpu().numpy() == -1).all()
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_table_all_hashes_equal(wide):
+    """Level-1 keys all zero: every key (one block each) hashes to b_1, so
+    every probe meets keys of equal hash and length whose bytes differ (the
+    probe's compare-every-candidate path)."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    say(f"case table all hashes equal: wide={wide}")
+    keys_np = U.keys_for(wide, 1 + wide).copy()
+    keys_np[:8 * 128] = 0  # every a = 0 (allowed: zero keys cannot overflow); b kept
+    kparts = key_set(400, 850, lo=4, hi=12, dup_every=3)
+    qparts = queries_for(kparts, 300, 851)
+    kbuf, koff = ragged(kparts)
+    qbuf, qoff = ragged(qparts)
+    keys = U.to_dev_keys(keys_np)
+    dk, dko = U.to_dev(W.Ragged(kbuf, koff, wide))
+    dq, dqo = U.to_dev(W.Ragged(qbuf, qoff, wide))
+    m = 64
+    t = pmp.pmp_table_build(wide, dk, dko, keys, m)
+    res = t.probe(dq, dqo)
+    torch.cuda.synchronize()
+    kh = oracle_hashes(wide, kbuf, koff, keys_np, 0)
+    qh = oracle_hashes(wide, qbuf, qoff, keys_np, 0)
+    assert len(set(kh.tolist())) == 1  # one hash for all keys
+    check_table(wide, kbuf, koff, kh, m, t.bucket_start.cpu().numpy(), entry_keys(t, koff, kh))
+    want_start, want_entries = T.build(kh, m)
+    want = T.probe(kbuf, koff, kh, want_start, want_entries, qbuf, qoff, qh, m)
+    got = res.cpu().numpy()
+    assert np.array_equal(got, want)
+    assert (got >= 0).sum() >= 140
