@@ -14,7 +14,7 @@
 //
 // Launches: (1) the number of units of each string of more than one block
 // (a unit is a quarter of a level-2 node: 32 blocks) and an exclusive scan
-// of those counts; (2) strings of one block, four lanes each; (3) one wave
+// of those counts; (2) strings of one block, two lanes each; (3) one wave
 // per unit, 8 lanes per block and 8 blocks at a time: each block's exact sum
 // is reduced over its 8 lanes and folded, and the unit's share of its node,
 // sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
 // is read with plain loads of the aligned dwords holding it (the one past it
 // only when misaligned); the word holding the pad is formed with guarded
 // reads.
-constexpr int SL = 4;
+constexpr int SL = 2;
 __global__ __launch_bounds__(256) void p128_short(P128Args A) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t s = t / SL;
