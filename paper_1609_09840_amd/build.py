@@ -58,20 +58,30 @@ def _run(cmd, verbose):
         print(err, file=sys.stderr)
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libpmp.so (always recompiles)."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
-    for s in SOURCES:
-        o = os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o")
-        _run([HIPCC, *FLAGS, "-c", os.path.join(CSRC, s), "-o", o], verbose)
-        objs.append(o)
-    rt = hip_runtime_dir()
-    tmp = LIB + ".tmp"
-    _run(["g++", "-shared", "-o", tmp, *objs, "-L" + rt, "-l:libamdhip64.so", "-Wl,-rpath," + rt,
-          "-pthread", "-Wl,--no-undefined", "-Wl,-z,now"], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+def build(verbose: bool = False, lib: str = LIB, build_dir: str = BUILD_DIR, extra: tuple = (),
+          runtime_dir: str | None = None, jobs: int = 0) -> str:
+    """Compile every source and link the library (always recompiles). ``extra``
+    adds compiler flags (a host-sanitizer build passes its flags here, each
+    behind -Xarch_host, into a build directory and library path of its own);
+    sources compile in parallel on ``jobs`` threads (default: one per
+    source, at most the host's CPU count)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(build_dir, exist_ok=True)
+    objs = [os.path.join(build_dir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1))
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    rt = runtime_dir or hip_runtime_dir()
+    tmp = lib + ".tmp"
+    link = ["g++", "-shared", "-o", tmp, *objs, "-L" + rt, "-l:libamdhip64.so", "-Wl,-rpath," + rt, "-pthread",
+            "-Wl,-z,now"]
+    if not extra:
+        link.append("-Wl,--no-undefined")  # a sanitizer build takes its runtime from LD_PRELOAD
+    _run(link, verbose)
+    os.replace(tmp, lib)
+    return lib
 
 
 def stale() -> bool:

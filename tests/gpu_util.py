@@ -16,9 +16,11 @@ def dev():
 
 
 def keys_for(wide: bool, seed: int):
-    from paper_1609_09840_amd import pmp
-
-    return pmp.pmp_expand_keys64(seed) if wide else pmp.pmp_expand_keys32(seed)
+    """Key table for seed, from the oracle's own expansion: no expected value
+    of a GPU test depends on a library output (the library's expansion is
+    compared with this one in test_keys.py)."""
+    o = oracle.load()
+    return o.expand_keys64(seed) if wide else o.expand_keys32(seed)
 
 
 def to_dev_keys(keys_np: np.ndarray):

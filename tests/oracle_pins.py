@@ -23,8 +23,14 @@ What pins what:
   mixers                    Sec. 7 printed constants (hand values) and
                             invertibility (an inverse written here).
   regularity                Lemma 9: with all other words fixed, the field
-                            output is a bijection of the swept word; the n-bit
-                            output has at most 2 preimages (Lemma 8).
+                            output is a bijection of the swept word (2^20
+                            contiguous values across the wrap past p); the
+                            n-bit output has at most 2 preimages, exactly k
+                            of them twice when a_r = 1 (Lemma 8).
+  single-key collisions     Lemma 9 / Sec. 5 bound: over one key a_r the
+                            field outputs of a fixed pair collide at exactly
+                            the t the modular inverse predicts, n-bit outputs
+                            at no more than three predicted t.
   key expansion             published splitmix64 outputs, key ranges of
                             Eq. (1) with kappa from Table "parameters".
 """
@@ -308,43 +314,130 @@ def pin_mixers(o):
             assert back == z
 
 
+def _sweep_word(o, wide, base: bytes, r: int, lo: int, n: int, keys, mode=O.FIELD):
+    """Outputs of the oracle for n copies of base whose word r takes the
+    values lo, lo + 1, ..., lo + n - 1 (one batch call: every copy is hashed
+    by the oracle in full)."""
+    W = 8 if wide else 4
+    L = len(base)
+    vals = np.arange(n, dtype=np.uint64) + np.uint64(lo)
+    buf = np.tile(np.frombuffer(base, np.uint8), n).reshape(n, L)
+    buf[:, r * W:(r + 1) * W] = vals.astype("<u8").view(np.uint8).reshape(n, 8)[:, :W]
+    off = np.arange(n + 1, dtype=np.int64) * L
+    out = o.batch(wide, buf.reshape(-1), off, keys, mode, nthreads=os.cpu_count() or 1)
+    if wide and mode == O.FIELD:
+        return [int(a) | (int(b) << 64) for a, b in out]
+    return [int(v) for v in out]
+
+
+def _preimage_counts(f, n):
+    raw = {}
+    for v in f:
+        raw[v % (1 << n)] = raw.get(v % (1 << n), 0) + 1
+    return raw
+
+
 def pin_regularity(o):
-    """Lemma 9 / Lemma 8, brute force over a swept word: with all other words
-    and all keys fixed, distinct values of word r give distinct field
-    outputs (an injective affine map), and n-bit outputs have at most two
-    preimages."""
+    """Lemma 9 (and Lemma 8 for the n-bit output), by brute force over a
+    contiguous window of 2^20 (PM+32) / 2^18 (PM+64) values of one word,
+    all other words and keys fixed:
+      - with a_{1,r} = 1 and one level the field output is v + C mod p, so
+        consecutive values step by exactly 1 mod p; the window is placed
+        where v + C wraps past p, so that exactly k = p - 2^n n-bit values
+        have two preimages (h and h - 2^n) and none has three;
+      - with a random a_{1,r}, and with the largest admissible one, at the
+        top of the word range, the field outputs are pairwise distinct and
+        step by a_{1,r} mod p, and no n-bit value has more than two
+        preimages;
+      - with two levels (the word in the second block) the field output is
+        still injective in the word."""
     rng = np.random.default_rng(18)
-    for wide, W in ((False, 4), (True, 8)):
+    for wide, W, p, amax, span in ((False, 4, P32, AMAX32, 1 << 20), (True, 8, P64, AMAX64, 1 << 18)):
+        n = 8 * W
         keys = o.expand_keys64(21) if wide else o.expand_keys32(21)
-        base = bytearray(rng.bytes(3 * W + 2))
-        seen_f, seen_r = set(), {}
-        vals = [int(v) for v in rng.choice(1 << 16, size=1500, replace=False)]
-        vals += [(1 << 8 * W) - 1 - v for v in range(40)]
-        for v in vals:
-            base[W:2 * W] = v.to_bytes(W, "little")
-            f = _h(o, wide, bytes(base), keys)[0]
-            assert f not in seen_f
-            seen_f.add(f)
-            r = f % (1 << 8 * W)
-            seen_r[r] = seen_r.get(r, 0) + 1
-            assert seen_r[r] <= 2
+        base = bytes(rng.bytes(3 * W + 2))  # four padded words, one level
+        r = 1
+        # a_{1,r} = 1: window across the wrap of v + C past p
+        k1 = keys.copy()
+        k1[r] = 1
+        c0 = _sweep_word(o, wide, base, r, 0, 1, k1)[0]  # C = output at v = 0
+        cross = (p - c0) % p  # first v with v + C >= p
+        assert span <= cross <= (1 << n) - span, "choose another base"
+        lo = cross - span // 2
+        f = _sweep_word(o, wide, base, r, lo, span, k1)
+        assert all((f[i + 1] - f[i]) % p == 1 for i in range(span - 1))
+        assert len(set(f)) == span
+        raw = _preimage_counts(f, n)
+        twice = sorted(k for k, c in raw.items() if c == 2)
+        assert max(raw.values()) == 2 and twice == list(range(p - (1 << n))), (wide, twice[:20])
+        # random key and the largest key, at the top of the word range
+        for a in (int(keys[r]), amax):
+            k2 = keys.copy()
+            k2[r] = a
+            f = _sweep_word(o, wide, base, r, (1 << n) - span, span, k2)
+            assert all((f[i + 1] - f[i]) % p == a % p for i in range(span - 1))
+            assert len(set(f)) == span
+            assert max(_preimage_counts(f, n).values()) <= 2
+        # two levels: the swept word in the second block
+        base2 = bytes(rng.bytes(128 * W + 3 * W))
+        f = _sweep_word(o, wide, base2, 128 + 1, 12345, 1 << 14, keys)
+        assert len(set(f)) == 1 << 14
 
 
-def pin_collision_bound(o):
-    """Almost-Delta-universality (Lemma 9, final bound 3L/(p-1-kappa)): over
-    random key tables, pairs of tiny distinct messages collide in their n-bit
-    output no more often than the bound allows (expected count far below 1)."""
-    msgs = [b"", b"\x00", b"\x01", b"\x00\x00\x00\x00", b"\x01\x00\x00\x00", b"a", b"b"]
-    draws = 300
-    for wide, p, kappa in ((False, P32, 28), (True, P64, 24)):
-        coll = 0
-        for s in range(draws):
-            keys = o.expand_keys64(1000 + s) if wide else o.expand_keys32(1000 + s)
-            outs = [_h(o, wide, m, keys, O.RAW)[0] for m in msgs]
-            coll += len(outs) - len(set(outs))
-        pairs = draws * len(msgs) * (len(msgs) - 1) // 2
-        bound = 3 * 1 / (p - 1 - kappa) * pairs
-        assert coll <= bound + 3 * (bound ** 0.5) + 1e-9, (wide, coll, bound)
+def pin_single_key_collisions(o):
+    """Almost-Delta-universality (Lemma 9, bound 3L/(p - 1 - kappa) of Sec. 5)
+    on one key: two equal-length one-level messages differing in words r and
+    s, every key fixed except a_{1,r} = t. Then h(x) - h(y) = t d_r + c mod p
+    with d_r = x_r - y_r and c fixed, so the field outputs collide for exactly
+    one t (t = -c / d_r mod p) and the n-bit outputs can collide only where
+    h(x) - h(y) is 0 or +-2^n, i.e. for at most three t. The oracle is swept
+    over windows of t around the three solutions the modular inverse gives
+    (plus random t over the whole range): the field collision must sit
+    exactly at the predicted t, n-bit collisions only at predicted values,
+    and the difference must step by d_r mod p between neighbouring t."""
+    rng = np.random.default_rng(19)
+    for wide, W, p, amax in ((False, 4, P32, AMAX32), (True, 8, P64, AMAX64)):
+        n = 8 * W
+        h = (o.pm64 if wide else o.pm32)
+        keys = o.expand_keys64(31) if wide else o.expand_keys32(31)
+        r, s_ = 2, 0
+        for _ in range(50):
+            x = bytearray(rng.bytes(3 * W + 1))
+            y = bytearray(x)
+            y[r * W:(r + 1) * W] = rng.bytes(W)
+            y[s_ * W:(s_ + 1) * W] = rng.bytes(W)
+            xw, yw = _words(bytes(x), W), _words(bytes(y), W)
+            d = [(a - b) % p for a, b in zip(xw, yw)]
+            c = sum(int(keys[i]) * d[i] for i in range(len(d)) if i != r) % p
+            inv = pow(d[r], -1, p)
+            t_star = (-c * inv) % p
+            cands = {t_star} | {((e - c) * inv) % p for e in (1 << n, p - (1 << n))}
+            if 1 <= t_star <= amax:
+                break
+        else:
+            raise AssertionError("no pair with an admissible colliding key")
+        half = 2048
+        ts = set()
+        for t0 in cands:
+            ts |= set(range(max(1, t0 - half), min(amax, t0 + half) + 1))
+        ts |= {int.from_bytes(rng.bytes(W), "little") % amax + 1 for _ in range(2000)}
+        field_hits, raw_hits = [], []
+        prev = None
+        for t in sorted(ts):
+            k = keys.copy()
+            k[r] = t
+            hx = h(bytes(x), k, O.FIELD)[0]
+            hy = h(bytes(y), k, O.FIELD)[0]
+            diff = (hx - hy) % p
+            if prev is not None and prev[0] == t - 1:
+                assert (diff - prev[1]) % p == d[r], (wide, t)
+            prev = (t, diff)
+            if hx == hy:
+                field_hits.append(t)
+            if hx % (1 << n) == hy % (1 << n):
+                raw_hits.append(t)
+        assert field_hits == [t_star], (wide, field_hits, t_star)
+        assert set(raw_hits) <= cands and t_star in raw_hits and len(raw_hits) <= 3, (wide, raw_hits)
 
 
 def pin_splitmix(o):
@@ -354,12 +447,55 @@ def pin_splitmix(o):
     assert got == want, [hex(g) for g in got]
 
 
+GAMMA = 0x9E3779B97F4A7C15
+_SM_MUL = (0xBF58476D1CE4E5B9, 0x94D049BB133111EB)
+
+
+def splitmix_seed_for(value: int, draw: int) -> int:
+    """The seed whose splitmix64 stream has ``value`` as output number ``draw``
+    (0-based): undo the finalizer (xorshifts and odd multipliers, inverted
+    here) to get the state, then step the golden gamma back. Used to force the
+    rejection path of the key expansion at a chosen draw."""
+    mask = (1 << 64) - 1
+    z = _inv_xorshift(value, 31, 64)
+    z = _inv_xorshift((z * pow(_SM_MUL[1], -1, 1 << 64)) & mask, 27, 64)
+    z = _inv_xorshift((z * pow(_SM_MUL[0], -1, 1 << 64)) & mask, 30, 64)
+    return (z - (draw + 1) * GAMMA) & mask
+
+
+def reject_seeds(wide: bool):
+    """(seed, draw, candidate) triples whose stream puts an out-of-range a
+    candidate (0 or above p - kappa - 1) or the largest admissible one at a
+    chosen draw: at the first draw, in the middle of level 1, and in the
+    last level."""
+    if wide:
+        vals = [(0, False), ((1 << 64) - 11, False), ((1 << 64) - 1, False), (AMAX64, True)]
+    else:
+        vals = [(0x12345678, False), (((1 << 32) - 13) << 32 | 7, False), (((1 << 32) - 1) << 32, False),
+                (AMAX32 << 32 | 0xFFFFFFFF, True)]
+    out = []
+    for (v, ok), draw in zip(vals, (0, 77, 900, 5)):
+        out.append((splitmix_seed_for(v, draw), draw, v >> (0 if wide else 32), ok))
+    return out
+
+
 def pin_key_expansion(o):
     """Key tables: a in [1, p - kappa - 1], drawn in storage order from the
     splitmix64 stream (PM+32 takes the top 32 bits of each output), candidates
-    outside the range skipped; b are the next 8 draws, unrestricted."""
+    outside the range skipped; b are the next 8 draws, unrestricted. Seeds
+    built by inverting the finalizer force a rejected candidate (or the
+    largest accepted one) at a chosen draw."""
     for wide, amax, shift in ((False, AMAX32, 32), (True, AMAX64, 0)):
-        for seed in (0, 1, 2, 12345):
+        forced = reject_seeds(wide)
+        for seed, draw, cand, ok in forced:
+            stream = [int(v) >> shift for v in o.splitmix64_stream(seed, draw + 1)]
+            assert stream[draw] == cand
+            k = o.expand_keys64(seed) if wide else o.expand_keys32(seed)
+            if ok:
+                assert int(k[draw]) == cand == amax
+            else:
+                assert cand not in [int(v) for v in k[:1024]]
+        for seed in (0, 1, 2, 12345) + tuple(f[0] for f in forced):
             k = o.expand_keys64(seed) if wide else o.expand_keys32(seed)
             stream = [int(v) >> shift for v in o.splitmix64_stream(seed, 1100)]
             acc = [c for c in stream if 1 <= c <= amax][:1024]

@@ -122,6 +122,40 @@ def test_server_device_requests_alone_equals_mix():
         assert U.first_mismatch(got, want) is None, ("mix vs oracle", U.first_mismatch(got, want))
 
 
+def test_server_48_full_c5_requests_alone_equals_mix():
+    """48 requests drawn exactly as the serving workload draws them (1..4096
+    strings, 16 B..64 KiB), device-resident, arriving as a Poisson stream
+    fast enough that launches overlap on four lanes: each output equals the
+    same request hashed alone and the oracle, bit for bit."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(1601)
+    reqs, keep = [], []
+    for k in range(48):
+        rg = W.c5_request(rng, 1610 + k)
+        buf, off = U.to_dev(rg)
+        out = torch.zeros(rg.count, dtype=out_dtype(rg.wide, 0), device=U.dev())
+        keep.append((rg, buf, off, out))
+        reqs.append(pmp.Server.request(rg.wide, buf, off, out))
+    arrivals = np.cumsum(rng.exponential(20.0, size=len(reqs)))  # mean gap 20 us: many in flight
+    say(f"case server 48 full C5 requests: {sum(k[0].nbytes for k in keep)} bytes")
+    srv = _server(lanes=4, lane_bytes=0, max_requests_per_batch=16)
+    lat = srv.replay(reqs, arrivals)
+    assert srv.status() == pmp.PMP_OK
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["completed"] == len(reqs) and np.all(lat > 0)
+    srv.close()
+    for i, (rg, buf, off, out) in enumerate(keep):
+        got = U.as_u64(out.cpu().numpy())
+        alone = U.gpu_hash(rg, U.keys_for(rg.wide, W.KEY_SEED64 if rg.wide else W.KEY_SEED32), 0, buf=buf, off=off)
+        want = oracle_of(rg)
+        assert U.first_mismatch(got, alone) is None, (i, "mix vs alone", U.first_mismatch(got, alone))
+        assert U.first_mismatch(got, want) is None, (i, "mix vs oracle", U.first_mismatch(got, want))
+
+
 def test_server_host_requests_and_admission():
     """Host requests are staged through the lane arenas; one larger than an
     arena is refused at submit; the rest complete with the oracle's values."""

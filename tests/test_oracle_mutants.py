@@ -59,3 +59,20 @@ def test_mutant_is_caught(src, name, old, new):
             except (AssertionError, oracle.OracleError):
                 failed.append(pin.__name__)
         assert failed, f"mutant {name} passed every pin"
+
+
+# the property pins of Lemma 9 / Lemma 8 must catch these on their own
+PROPERTY_MUTANTS = ["wrong_prime32", "wrong_prime64", "keys_reversed", "level_keys_swapped"]
+
+
+@pytest.mark.parametrize("name", PROPERTY_MUTANTS)
+def test_property_pins_bite(src, name):
+    old, new = next((m[1], m[2]) for m in MUTANTS if m[0] == name)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        o = oracle.load(oracle.build(path, os.path.join(d, "libm.so")))
+        for pin in (oracle_pins.pin_regularity, oracle_pins.pin_single_key_collisions):
+            with pytest.raises((AssertionError, oracle.OracleError)):
+                pin(o)
