@@ -492,8 +492,22 @@ def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505, pe
     mean_bytes = float(np.mean([p[0].nbytes for p in pool]))
     k32 = torch.from_numpy(pmp.pmp_expand_keys32(W.KEY_SEED32).view(np.int32)).to(dev).view(torch.uint32)
     k64 = torch.from_numpy(pmp.pmp_expand_keys64(W.KEY_SEED64).view(np.int64)).to(dev).view(torch.uint64)
+    # one request alone: host wall time of one launch and its completion (the floor of a request's latency)
+    plan = pmp.Plan(0)
+    stream = torch.cuda.current_stream()
+    alone = []
+    for rep in range(3):
+        for rg, buf, off, out in pool:
+            b = pmp.make_batch(rg.wide, buf, off, k64 if rg.wide else k32, out)
+            t0 = time.perf_counter()
+            pmp.pmp_hash_many([b], plan=plan, stream=stream)
+            stream.synchronize()
+            if rep:
+                alone.append((time.perf_counter() - t0) * 1e3)
+    plan.close()
+    budget = 1 << 30
     srv = pmp.Server(k32, k64, device=0, lanes=4, lane_bytes=0, max_requests_per_batch=per_launch,
-                     reserve_bytes=64 << 20)
+                     max_inflight_bytes=budget, idle_spin_us=200)
     try:
         srv.replay(reqs, np.zeros(len(reqs)))  # warm-up
         srv.reset_stats()
@@ -520,7 +534,10 @@ def serving_sweep(dev, pool_size: int = 48, points: int = 8, seed: int = 505, pe
     host = serving_host(pool, k32, k64, per_launch)
     return {"mean_request_bytes": round(mean_bytes), "saturation_rps": round(float(sat_rps), 2),
             "saturation_GBps": round(sat_rps * mean_bytes / 1e9, 2), "lanes": 4,
-            "max_requests_per_launch": per_launch,
+            "max_requests_per_launch": per_launch, "max_inflight_bytes": budget, "idle_spin_us": 200,
+            "alone_ms_p50": round(float(np.percentile(alone, 50)), 4),
+            "alone_ms_p99": round(float(np.percentile(alone, 99)), 4),
+            "alone_note": "one request of the pool hashed by itself: host wall time of its launch and completion",
             "payload": "device-resident pool of %d requests" % pool_size, "sweep": rows,
             "host_staged": host}
 
@@ -586,6 +603,7 @@ def main():
     ap.add_argument("--no-pm128", action="store_true", help="skip the PM+128 pass")
     ap.add_argument("--pm128-only", action="store_true", help="only run the PM+128 pass and print its JSON")
     ap.add_argument("--table-only", action="store_true", help="only run the hash-table pass and print its JSON")
+    ap.add_argument("--serve-only", action="store_true", help="only run the serving sweep and print its JSON")
     ap.add_argument("--incr-pieces", default="1048576,16777216,268435456",
                     help="piece sizes of the incremental pass, in bytes, comma-separated")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -617,6 +635,9 @@ def main():
         return
     if args.table_only:
         print(json.dumps({"hash_table": hash_table(dev)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_sweep(dev)}), flush=True)
         return
     if args.incr_only:
         print(json.dumps({"incremental": incremental(dev, pieces=incr_pieces)}), flush=True)

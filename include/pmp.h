@@ -223,7 +223,18 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
  *     before the request counts as complete. Such a request must fit the
  *     arena (16-byte rounded payload + offsets + output <= lane_bytes), else
  *     submit returns PMP_E_NOMEM ("admission by memory"); a request that fits
- *     waits in the queue until a lane has room.
+ *     waits in the queue until a lane has room. Its offsets are checked at
+ *     submit (PMP_E_OFFSETS if out of order or past buf_bytes).
+ * Device-resident requests are admitted against max_inflight_bytes: the
+ * payload bytes of the batches on the device never exceed it (a request
+ * larger than the budget is refused at submit with PMP_E_NOMEM), and every
+ * lane's plan is sized for it at creation, so the loop does not allocate.
+ * Offsets of a device-resident request are checked by the kernel: a batch
+ * that flags bad offsets is hashed again one request at a time, and only the
+ * requests with bad offsets fail (pmp_server_wait returns PMP_E_OFFSETS);
+ * the others complete with their correct outputs.
+ * While a lane is busy or a request is queued, the dispatcher polls without
+ * sleeping; when idle it polls for idle_spin_us before it sleeps.
  * Latency is measured from submit to completion (results visible in `out`).
  * Outputs are bit-identical to hashing the request alone with pmp_hash32/64. */
 typedef struct pmp_server pmp_server;
@@ -237,6 +248,10 @@ typedef struct pmp_server_config {
   int max_requests_per_batch;     /* >= 1 */
   int64_t max_batch_strings;      /* strings per launch before a lane closes (0: no limit) */
   uint64_t reserve_bytes;         /* pre-size each lane's plan for this much buffer (0: grow on use) */
+  uint64_t max_inflight_bytes;    /* device-resident payload bytes in flight over all lanes (0: no limit) */
+  int32_t idle_spin_us;           /* when idle, the dispatcher polls for work this long before it
+                                     sleeps (0..1000000; 0: sleep at once) */
+  int32_t reserved;
 } pmp_server_config;
 
 typedef struct pmp_request {
@@ -253,6 +268,7 @@ typedef struct pmp_request {
 
 typedef struct pmp_server_report {
   uint64_t completed, rejected, batches, bytes; /* bytes: payload bytes hashed */
+  uint64_t failed;                              /* requests that completed with an error */
   double p50_us, p99_us, max_us, mean_us;       /* submit-to-completion latency */
   double span_us;                               /* first submit to last completion */
 } pmp_server_report;
@@ -264,8 +280,8 @@ int pmp_server_destroy(pmp_server* server);
 int pmp_server_submit(pmp_server* server, const pmp_request* req, uint64_t* ticket);
 /* Wait for a request: timeout_us < 0 waits for ever. Returns 1 if it is still
  * pending at the timeout (the ticket stays valid), else its final status
- * (PMP_OK or a PMP_E_* code) and releases the ticket. Device-side problems
- * (bad offsets) show in pmp_server_status, not here. */
+ * (PMP_OK or a PMP_E_* code, PMP_E_OFFSETS for offsets the kernel found
+ * bad) and releases the ticket. */
 int pmp_server_wait(pmp_server* server, uint64_t ticket, int64_t timeout_us);
 /* Latency and throughput over the requests completed since the last reset. */
 int pmp_server_stats(pmp_server* server, pmp_server_report* stats);

@@ -303,6 +303,15 @@ int current_plan(pmp_plan** plan, hipStream_t stream) {
 
 namespace pmp {
 
+int32_t* plan_status_word(pmp_plan* plan) { return plan ? plan->status : nullptr; }
+
+int plan_clear_async(pmp_plan* plan, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(plan->mu);
+  hipError_t e = hipMemsetAsync(plan->status, 0, sizeof(int32_t), stream);
+  if (e == hipSuccess && plan->slots) e = hipMemsetAsync(plan->slots, 0, plan->nslots * sizeof(Slot), stream);
+  return e == hipSuccess ? PMP_OK : hip_fail(e, "hipMemsetAsync");
+}
+
 // Hash n batches in one launch.
 int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream) {
   std::vector<const pmp_batch*> list;

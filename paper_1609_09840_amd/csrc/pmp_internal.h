@@ -13,6 +13,10 @@ namespace pmp {
 // host side (pmp_api.cpp)
 int set_error(int code, const char* msg);  // sets the message pmp_last_error returns
 int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream);
+// a plan's device status word, and a clear of it and of the plan's node
+// accumulators ordered on `stream` (after a launch that flagged an error)
+int32_t* plan_status_word(pmp_plan* plan);
+int plan_clear_async(pmp_plan* plan, hipStream_t stream);
 
 // kernels/launchers (pmp_kernels.hip)
 hipError_t launch_batch(const KArgs& a, int grid, int g32, int g64, hipStream_t s);

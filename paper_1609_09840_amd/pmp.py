@@ -57,6 +57,9 @@ class pmp_server_config(ctypes.Structure):
         ("max_requests_per_batch", ctypes.c_int),
         ("max_batch_strings", ctypes.c_int64),
         ("reserve_bytes", ctypes.c_uint64),
+        ("max_inflight_bytes", ctypes.c_uint64),
+        ("idle_spin_us", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -91,6 +94,7 @@ class pmp_server_report(ctypes.Structure):
         ("rejected", ctypes.c_uint64),
         ("batches", ctypes.c_uint64),
         ("bytes", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64),
         ("p50_us", ctypes.c_double),
         ("p99_us", ctypes.c_double),
         ("max_us", ctypes.c_double),
@@ -530,12 +534,14 @@ class Server:
     key tables given here (device tensors, uint32[1032] and uint64[1032])."""
 
     def __init__(self, keys32, keys64, device: int = 0, lanes: int = 2, lane_bytes: int = 64 << 20,
-                 max_requests_per_batch: int = 256, max_batch_strings: int = 0, reserve_bytes: int = 0):
+                 max_requests_per_batch: int = 256, max_batch_strings: int = 0, reserve_bytes: int = 0,
+                 max_inflight_bytes: int = 0, idle_spin_us: int = 200):
         self._keys = (keys32, keys64)  # keep the tables alive
         cfg = pmp_server_config(device=device, lanes=lanes, lane_bytes=lane_bytes,
                                 d_keys32=_dev_ptr(keys32, "keys32"), d_keys64=_dev_ptr(keys64, "keys64"),
                                 max_requests_per_batch=max_requests_per_batch,
-                                max_batch_strings=max_batch_strings, reserve_bytes=reserve_bytes)
+                                max_batch_strings=max_batch_strings, reserve_bytes=reserve_bytes,
+                                max_inflight_bytes=max_inflight_bytes, idle_spin_us=idle_spin_us)
         h = ctypes.c_void_p()
         _check(_lib.pmp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

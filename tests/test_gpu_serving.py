@@ -156,6 +156,96 @@ def test_server_48_full_c5_requests_alone_equals_mix():
         assert U.first_mismatch(got, want) is None, (i, "mix vs oracle", U.first_mismatch(got, want))
 
 
+def test_server_bad_offsets_fail_only_their_request():
+    """A device-resident request with decreasing offsets, submitted with good
+    ones so that they share a launch: only it fails (PMP_E_OFFSETS), the
+    others, and the requests after it on the same lane, match the oracle.
+    A host request with bad offsets is refused at submit."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(1701)
+    srv = _server(lanes=1, lane_bytes=8 << 20, max_requests_per_batch=8)
+    keep, tickets = [], []
+    bad = W.from_lengths([10, 20, 30, 40], 1702, False)
+    offs = bad.offsets.copy()
+    offs[2] = offs[1] - 5  # string 1 runs backwards
+    bad_buf = torch.from_numpy(bad.buf).to(U.dev())
+    bad_off = torch.from_numpy(offs).to(U.dev())
+    bad_out = torch.zeros(4, dtype=torch.uint32, device=U.dev())
+    say("case server bad offsets: 1 bad request among 11")
+    for k in range(11):
+        if k == 3:
+            tickets.append(srv.submit(pmp.Server.request(False, bad_buf, bad_off, bad_out)))
+            keep.append(None)
+            continue
+        rg = small_request(rng, 1710 + k, max_count=128)
+        buf, off = U.to_dev(rg)
+        out = torch.zeros(rg.count, dtype=out_dtype(rg.wide, 0), device=U.dev())
+        keep.append((rg, buf, off, out))
+        tickets.append(srv.submit(pmp.Server.request(rg.wide, buf, off, out)))
+    for k, t in enumerate(tickets):
+        if k == 3:
+            with pytest.raises(pmp.PmpError) as ei:
+                srv.wait(t)
+            assert ei.value.code == pmp.PMP_E_OFFSETS
+        else:
+            assert srv.wait(t) == pmp.PMP_OK
+    hbad = W.from_lengths([10, 20], 1703, False)
+    hoffs = hbad.offsets.copy()
+    hoffs[-1] = hbad.buf.size + 1  # past the payload
+    with pytest.raises(pmp.PmpError) as ei:
+        srv.submit(pmp.Server.request(False, hbad.buf, hoffs, np.zeros(2, np.uint32)))
+    assert ei.value.code == pmp.PMP_E_OFFSETS
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["failed"] == 1 and st["completed"] == 10
+    assert srv.status() == pmp.PMP_OK
+    srv.close()
+    for item in keep:
+        if item is None:
+            continue
+        rg, buf, off, out = item
+        want = oracle_of(rg)
+        assert U.first_mismatch(U.as_u64(out.cpu().numpy()), want) is None
+
+
+def test_server_inflight_budget():
+    """Device-resident requests admitted against an in-flight byte budget:
+    one larger than the budget is refused at submit; the rest complete
+    exactly while never more than the budget is on the device at once."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(1801)
+    budget = 2 << 20
+    srv = _server(lanes=4, lane_bytes=0, max_requests_per_batch=16, max_inflight_bytes=budget)
+    big = W.from_lengths([budget + 1], 1802, False)
+    bbuf, boff = U.to_dev(big)
+    bout = torch.zeros(1, dtype=torch.uint32, device=U.dev())
+    with pytest.raises(pmp.PmpError) as ei:
+        srv.submit(pmp.Server.request(False, bbuf, boff, bout))
+    assert ei.value.code == pmp.PMP_E_NOMEM
+    reqs, keep = [], []
+    for k in range(30):
+        rg = small_request(rng, 1810 + k, max_count=64)
+        buf, off = U.to_dev(rg)
+        out = torch.zeros(rg.count, dtype=out_dtype(rg.wide, 0), device=U.dev())
+        keep.append((rg, buf, off, out))
+        reqs.append(pmp.Server.request(rg.wide, buf, off, out))
+    say(f"case server budget: {len(reqs)} requests, {sum(k[0].nbytes for k in keep)} bytes, budget {budget}")
+    srv.replay(reqs, np.zeros(len(reqs)))
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["completed"] == len(reqs) and st["rejected"] == 1
+    assert srv.status() == pmp.PMP_OK
+    srv.close()
+    for rg, buf, off, out in keep:
+        assert U.first_mismatch(U.as_u64(out.cpu().numpy()), oracle_of(rg)) is None
+
+
 def test_server_host_requests_and_admission():
     """Host requests are staged through the lane arenas; one larger than an
     arena is refused at submit; the rest complete with the oracle's values."""
