@@ -264,6 +264,72 @@ def cpu_baseline(wl, target_cpu_s: float = 12.0):
     }
 
 
+def other_configs(dev, names=("c1", "c2", "c3"), steps: int = 20) -> dict:
+    """The other configurations of the hot path, each in the bench's launch
+    form (the library's autotuner on the workload, then one launch per step,
+    `steps` back to back between two HIP events on the launch stream):
+    C1 in microseconds per batch (median and p99 of launches timed one by
+    one, and the mean of back-to-back launches); C2 and C3 in GB/s with the
+    roofline fraction of their algorithmic bytes, HBM traffic from their
+    committed counters, the plain one-string-per-launch form on a prefix and
+    the oracle on a bounded sample."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+    from paper_1609_09840_amd import workloads as W
+
+    res = {}
+    for name in names:
+        wl = W.CONFIGS[name]()
+        keep, batches = setup(wl, dev)
+        stream = torch.cuda.current_stream()
+        plan = pmp.Plan(0)
+        plan.reserve(sum(rg.buf.size for rg in wl.batches), wl.count)
+        tuning = pmp.pmp_plan_autotune(plan, [b for b in batches if b is not None], stream=stream)
+
+        def step():
+            pmp.pmp_hash_mixed(batches[0], batches[1], stream=stream, plan=plan)
+
+        for _ in range(3):
+            step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if plan.status() != pmp.PMP_OK:
+            raise RuntimeError(f"{name}: device status not OK")
+        ms = e0.elapsed_time(e1) / steps
+        alg = algorithmic_bytes(wl)
+        r = {"workload": f"{name}: {DESCR[name]}", "strings": wl.count, "payload_bytes": wl.nbytes,
+             "tuning": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in tuning.items()},
+             "mean_launch_ms": round(ms, 5)}
+        if name == "c1":  # latency-bound: microseconds per batch
+            spread = launch_spread(step, plan, [b for b in batches if b is not None], stream)
+            r.update({"unit": "us per batch", "value": round(ms * 1e3, 2),
+                      "launch_us_median": round(spread["launch_ms_median"] * 1e3, 2),
+                      "launch_us_p99": round(spread["launch_ms_p99"] * 1e3, 2),
+                      "graph_replay_us": round(spread["graph_replay_ms"] * 1e3, 2),
+                      "note": "64 KiB per batch: launch latency, not bandwidth, bounds it"})
+        else:
+            achieved = alg / (ms * 1e-3) / 1e9
+            r.update({"unit": "GB/s", "value": round(wl.nbytes / (ms * 1e-3) / 1e9, 1),
+                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                   "traffic": read_traffic(name), "kernel": KERNEL,
+                                   "algorithmic_bytes_per_launch": alg,
+                                   "frac_of_achievable": round(achieved / achievable_read_gbs(dev), 4)}})
+        r["plain_gpu"] = plain_gpu(keep, dev, max_strings=8 if name == "c3" else 4000)
+        r["cpu_oracle"] = cpu_baseline(wl, target_cpu_s=3.0)
+        res[name] = r
+        plan.close()
+        del keep, batches
+        torch.cuda.empty_cache()
+    return res
+
+
 def plain_gpu(keep, dev, max_strings: int = 4000):
     """The one-string-per-launch GPU form on a prefix of each batch."""
     import torch
@@ -274,7 +340,7 @@ def plain_gpu(keep, dev, max_strings: int = 4000):
     tot_bytes, tot_s, nstr = 0, 0.0, 0
     share = max_strings / sum(k[0].count for k in keep)
     for rg, kn, buf, off, keys, out in keep:
-        n = max(1, int(rg.count * share))
+        n = max(1, min(rg.count, int(rg.count * share)))
         h = rg.offsets[: n + 1]
         o = torch.empty(n, dtype=out.dtype, device=dev)
         pmp.pmp_hash_plain(rg.wide, buf, h, keys, o, 0, scratch)  # warm
@@ -591,6 +657,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain GPU form")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1, C2 and C3 passes")
+    ap.add_argument("--configs-only", action="store_true", help="only run the C1, C2 and C3 passes")
     ap.add_argument("--g32", type=int, default=0, help="lanes per block, PM+32 (0: default)")
     ap.add_argument("--g64", type=int, default=0, help="lanes per block, PM+64 (0: default)")
     ap.add_argument("--waves-per-cu", type=int, default=0, help="waves per CU (0: as many as stay resident)")
@@ -635,6 +703,9 @@ def main():
         return
     if args.table_only:
         print(json.dumps({"hash_table": hash_table(dev)}), flush=True)
+        return
+    if args.configs_only:
+        print(json.dumps({"configs": other_configs(dev)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_sweep(dev)}), flush=True)
@@ -731,6 +802,8 @@ def main():
         raise RuntimeError("device status not OK after the spread pass")
     if not args.no_plain:
         rec["plain_gpu"] = plain_gpu(keep, dev)
+    if not args.no_configs:
+        rec["configs"] = other_configs(dev)
     if not args.no_serve:
         rec["serving"] = serving_sweep(dev)
     if not args.no_incr:
