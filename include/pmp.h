@@ -167,6 +167,23 @@ typedef struct pmp_batch {
 /* Hash up to two batches (any mix of PM+32 and PM+64) in ONE kernel launch;
  * either pointer may be NULL. Same semantics per batch as pmp_hash32/64. */
 int pmp_hash_mixed(pmp_plan* plan, const pmp_batch* b0, const pmp_batch* b1, pmp_stream_t stream);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pmp_hash_mixed
+ * without a plan, with the same outputs. The node accumulators live in a
+ * static device array of PMP_NOALLOC_SCRATCH_BYTES per device (16 bytes per
+ * 128-word block of each batch's buffer, plus 2 per batch: up to about
+ * 512 MiB of PM+32 or 1 GiB of PM+64 buffer), held until the process ends.
+ * Batches that need more return PMP_E_NOMEM before anything is queued.
+ * d_status: caller-owned device int32; the call sets it to 0, and the kernel
+ * ORs in 1 for offsets out of order or past buf_bytes (those strings get no
+ * output) and 2 for an internal workspace fault. The call queues a fill
+ * kernel (it clears the accumulators it uses and *d_status) and the hash
+ * kernel on `stream`, asynchronously, and allocates nothing. All calls on
+ * one device share the array: calls that overlap on one device race (the
+ * same stream orders them). Tiles and work weight are the library defaults. */
+#define PMP_NOALLOC_SCRATCH_BYTES (16u << 20)
+int pmp_hash_mixed_noalloc(const pmp_batch* b0, const pmp_batch* b1, int32_t* d_status, pmp_stream_t stream);
 /* Hash any number of batches (a HOST array of nbatch descriptors) in ONE
  * kernel launch; each batch keeps its own buffer, offsets, keys, output and
  * flags. With more than two batches the descriptors are uploaded to the

@@ -312,6 +312,38 @@ int plan_clear_async(pmp_plan* plan, hipStream_t stream) {
   return e == hipSuccess ? PMP_OK : hip_fail(e, "hipMemsetAsync");
 }
 
+// Up to two batches in one launch with workspace the caller brings: `slots`
+// node accumulators (nslots of them, zero on entry, left zero by a launch
+// whose offsets are in order) and the status word; `cus` and `per_cu` size
+// the grid. Nothing is allocated: the plan below lives on the stack and
+// only describes that workspace, with the default tiles and work weight.
+int run_static(const pmp_batch* const* in, int n_in, Slot* slots, uint64_t nslots, int32_t* status, int cus,
+               hipStream_t stream) {
+  std::vector<const pmp_batch*> list;
+  int r = collect(in, n_in, list);
+  if (r || list.empty()) return r;
+  uint64_t need = 0;
+  for (const pmp_batch* b : list) need += slots_for(b->buf_bytes, (int)b->wide);
+  if (need > nslots)
+    return fail(PMP_E_NOMEM, "the batches need %llu node accumulators (16 bytes each); the static scratch holds %llu",
+                (unsigned long long)need, (unsigned long long)nslots);
+  pmp_plan plan;  // no device memory of its own
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  plan.device = dev;
+  plan.cus = cus;
+  plan.slots = slots;
+  plan.nslots = nslots;
+  plan.status = status;
+  Prepared P;
+  r = prepare(&plan, list, P);  // need <= nslots: the workspace is not grown
+  if (r) return r;
+  e = launch_batch(P.a, P.grid, plan.g32, plan.g64, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  return PMP_OK;
+}
+
 // Hash n batches in one launch.
 int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream) {
   std::vector<const pmp_batch*> list;

@@ -13,6 +13,9 @@ namespace pmp {
 // host side (pmp_api.cpp)
 int set_error(int code, const char* msg);  // sets the message pmp_last_error returns
 int run_batches(pmp_plan* plan, const pmp_batch* const* in, int n_in, hipStream_t stream);
+// at most two batches, on caller-given node accumulators and status word, no allocation
+int run_static(const pmp_batch* const* in, int n_in, Slot* slots, uint64_t nslots, int32_t* status, int cus,
+               hipStream_t stream);
 // a plan's device status word, and a clear of it and of the plan's node
 // accumulators ordered on `stream` (after a launch that flagged an error)
 int32_t* plan_status_word(pmp_plan* plan);

@@ -21,6 +21,7 @@ PMP_E_TOO_LONG = -3
 PMP_E_OFFSETS = -4
 PMP_E_HIP = -5
 PMP_E_NOMEM = -6
+PMP_NOALLOC_SCRATCH_BYTES = 16 << 20  # include/pmp.h
 PMP_E_INTERNAL = -7
 
 PMP_NO_MIX = 1
@@ -130,6 +131,7 @@ def _load():
         "pmp_hash32": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash64": [vp, vp, u64, vp, i64, vp, vp, u32, vp],
         "pmp_hash_mixed": [vp, ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp],
+        "pmp_hash_mixed_noalloc": [ctypes.POINTER(pmp_batch), ctypes.POINTER(pmp_batch), vp, vp],
         "pmp_hash_many": [vp, ctypes.POINTER(pmp_batch), i32, vp],
         "pmp_graph_create": [vp, ctypes.POINTER(pmp_batch), i32, ctypes.POINTER(vp)],
         "pmp_graph_launch": [vp, vp],
@@ -370,6 +372,15 @@ def pmp_hash_mixed(b0: pmp_batch | None, b1: pmp_batch | None, stream=None, plan
     p0 = ctypes.byref(b0) if b0 is not None else None
     p1 = ctypes.byref(b1) if b1 is not None else None
     _check(_lib.pmp_hash_mixed(_plan_ptr(plan), p0, p1, _stream(stream)))
+
+
+def pmp_hash_mixed_noalloc(b0, b1, status, stream=None):
+    """pmp_hash_mixed on the library's static scratch (no allocation by the
+    library); `status` is a device int32 tensor of one element that receives
+    the status bits."""
+    _check(_lib.pmp_hash_mixed_noalloc(ctypes.byref(b0) if b0 is not None else None,
+                                       ctypes.byref(b1) if b1 is not None else None,
+                                       _dev_ptr(status, "status"), _stream(stream)))
 
 
 def pmp_hash_many(batches, stream=None, plan: Plan | None = None):
