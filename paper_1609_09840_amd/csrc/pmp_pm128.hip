@@ -126,6 +126,11 @@ __device__ F128 fold(const A5& S) {
   return z;
 }
 
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
 __device__ __forceinline__ const uint8_t* gp16(uint64_t a) {
   return (const uint8_t*)(const __attribute__((address_space(1))) uint8_t*)(uintptr_t)a;
 }
@@ -236,63 +241,144 @@ __device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
   return lo;
 }
 
-// Unit g: part k of string s's level-2 nodes (blocks QB k ..). The wave
-// takes 8 blocks at a time, 8 lanes per block: lane j of a group sums words
-// j, j + 8, ..., j + 120 of its block (16-byte loads, 128 contiguous bytes
-// per group and instruction), the group adds its eight sums (three steps),
-// folds, and multiplies by the block's level-2 key. A block of data words
-// only is read with plain loads of the aligned dwords holding each word (the
-// one past it only when misaligned); the string's last block is padded and
-// read with guarded loads.
-__device__ void node_unit(const P128Args& A, int64_t g, int lane) {
+// ---------------------------------------------------------------------------
+// Exact sums of 128 x 128 products from 32 x 32 -> 64 partial products:
+// with a = sum a_i 2^(32 i) and x = sum x_j 2^(32 j), a x = sum over the
+// diagonals d = i + j of (sum a_i x_j) 2^(32 d); diagonal d is kept as
+// acc[d] + 2^64 cnt[d] (v_mad_u64_u32 with its carry counted), and turned
+// into five 64-bit limbs once per block.
+struct D7 {
+  uint64_t acc[7];
+  uint32_t cnt[7];
+};
+__device__ __forceinline__ void zero(D7& s) {
+#pragma unroll
+  for (int d = 0; d < 7; ++d) {
+    s.acc[d] = 0;
+    s.cnt[d] = 0;
+  }
+}
+__device__ __forceinline__ void mac128(D7& s, const uint32_t* a, const uint32_t* x) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mac_vv(s.acc[i + j], s.cnt[i + j], a[i], x[j]);
+}
+// s += v at 64-bit limb k (k <= 4), carries up to limb 4
+__device__ __forceinline__ void add_limb(A5& s, uint64_t v, int k) {
+  uint64_t c = v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    if (i < k) continue;
+    const uint64_t t = s.w[i] + c;
+    c = t < c ? 1u : 0u;
+    s.w[i] = t;
+  }
+}
+__device__ __forceinline__ A5 collapse(const D7& s) {
+  A5 r;
+  zero(r);
+#pragma unroll
+  for (int d = 0; d < 7; ++d) {
+    const int m = d >> 1;
+    if ((d & 1) == 0) {
+      add_limb(r, s.acc[d], m);
+      if (m + 1 < 5) add_limb(r, s.cnt[d], m + 1);
+    } else {
+      add_limb(r, s.acc[d] << 32, m);
+      add_limb(r, (s.acc[d] >> 32) | ((uint64_t)s.cnt[d] << 32), m + 1);
+    }
+  }
+  return r;
+}
+
+template <int CTRL>
+__device__ __forceinline__ A5 dpp5(const A5& s) {
+  A5 r;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.w[i] = dpp<CTRL>(s.w[i]);
+  return r;
+}
+// sum over aligned groups of 16 lanes, every lane of a group ends with it
+__device__ __forceinline__ void group16_sum(A5& s) {
+  add(s, dpp5<0xB1>(s));
+  add(s, dpp5<0x4E>(s));
+  add(s, dpp5<0x141>(s));
+  add(s, dpp5<0x140>(s));
+}
+
+constexpr uint32_t OUTSIDE = 0x80000000u;  // past every buffer resource's end
+
+// Word w (its four dwords realigned by sh, then masked to the padded string
+// of Sec. 4: r = string bytes from the word's start) from the five dwords
+// d[] read at its 4-aligned start.
+__device__ __forceinline__ void word_dwords(const uint32_t* d, uint32_t sh, bool tail, int64_t r, uint32_t* x) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    x[u] = align_bytes(d[u + 1], d[u], sh);
+    if (tail) x[u] = tail_word32(x[u], r - 4 * u);
+  }
+}
+
+// Unit g: part k of string s's level-2 nodes (blocks QB k .. QB k + 31). The
+// wave takes 4 blocks at a time, 16 lanes per block: lane j of a group holds
+// words j, j + 16, ..., j + 112 of its block, all eight read at once through
+// a buffer resource over the unit's bytes (range-checked per dword by the
+// hardware: reads past the string's last dword are zeros, nothing is
+// fetched for them), with the level-1 keys from LDS. The group adds its
+// sixteen sums, folds, and multiplies by the block's level-2 key; the
+// unit's share of its node is reduced and stored.
+constexpr int GW = 16;              // lanes per block
+constexpr int WPL = BLOCK / GW;     // words per lane and block
+constexpr int BPS = 64 / GW;        // blocks per wave step
+__device__ void node_unit(const P128Args& A, const uint32_t* lk, int64_t g, int lane) {
   const int64_t s = unit_string(A, g, lane);
   const int64_t k = g - A.start[s];
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const uint8_t* str = A.buf + (len ? A.off[s] : 0);
-  const uint8_t* blo = A.buf;
-  const uint8_t* bhi = A.buf + A.buf_bytes;
   const int64_t n1 = blocks_of(len);
-  const int grp = lane / 8, j = lane % 8;
+  const int grp = lane / GW, j = lane % GW;
   const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
-
-  A5 node;  // this group's blocks' share of the node
-  zero(node);
   const int64_t c0 = k * QB;
   const int64_t c1 = c0 + QB < n1 ? c0 + QB : n1;
-  for (int64_t cb = c0; cb < c1; cb += 8) {
+  // the unit's bytes: from its first block (4-aligned) to the dword holding
+  // the string's last byte (which lies in the buffer's pages)
+  const uint64_t ubase = ((uint64_t)(uintptr_t)str - sh) + (uint64_t)c0 * BLK_BYTES;
+  const uint64_t span = (((uint64_t)sh + (uint64_t)len + 3) & ~3ull) - (uint64_t)c0 * BLK_BYTES;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(uintptr_t)uni64(ubase), (short)0, (int)(span < 0x7fffffffull ? span : 0x7fffffffull), 0x00020000);
+  A5 node;  // this group's blocks' share of the node (its lane 0)
+  zero(node);
+  for (int64_t cb = c0; cb < c1; cb += BPS) {
     const int64_t c = cb + grp;
-    A5 sum;
-    zero(sum);
-    if (c < c1) {
-      const bool full = c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES <= len;
-#pragma unroll 2
-      for (int t = 0; t < 16; ++t) {
-        const int64_t w = c * BLOCK + j + 8 * t;
-        uint64_t x0, x1, a0, a1;
-        if (full) {
-          const uint64_t a4 = (uint64_t)(uintptr_t)(str + W16 * w) - sh;
-          const Q q = load16(gp16(a4));
-          const uint32_t d4 = sh ? *(const uint32_t*)gp16(a4 + 16) : 0u;
-          const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], d4};
-          uint32_t x[4];
+    const bool act = c < c1;
+    uint32_t d[WPL][5];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
-          x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
-          x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
-        } else {
-          word128(str, len, w, blo, bhi, &x0, &x1);
-        }
-        key_a(A.keys, 1, (uint32_t)(j + 8 * t), &a0, &a1);
-        mac(sum, a0, a1, x0, x1);
-      }
+    for (int t = 0; t < WPL; ++t) {
+      const uint32_t o = act ? (uint32_t)(c - c0) * (uint32_t)BLK_BYTES + 16u * (uint32_t)(j + GW * t) : OUTSIDE;
+      const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
+      d[t][0] = q[0];
+      d[t][1] = q[1];
+      d[t][2] = q[2];
+      d[t][3] = q[3];
+      d[t][4] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 16u, 0, 0);
     }
-    for (int m = 1; m < 8; m <<= 1) {  // the block's sum in every lane of the group
-      A5 o;
+    __builtin_amdgcn_sched_barrier(0);  // every load of the step is issued before any is used
+    const bool tail = __ballot(act && c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES > len) != 0;
+    D7 acc;
+    zero(acc);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) o.w[i] = shx64(sum.w[i], m);
-      add(sum, o);
+    for (int t = 0; t < WPL; ++t) {
+      const int w = j + GW * t;
+      uint32_t x[4];
+      word_dwords(d[t], sh, tail, len - W16 * (c * BLOCK + w), x);
+      const uint4 kv = *(const uint4*)(lk + 4 * w);  // a_{1,w} as four 32-bit limbs
+      const uint32_t a[4] = {kv.x, kv.y, kv.z, kv.w};
+      mac128(acc, a, x);
     }
-    if (c < c1 && j == 0) {
+    A5 sum = collapse(acc);
+    group16_sum(sum);
+    if (act && j == 0) {
       add_b(sum, A.keys, 1);
       const F128 z1 = fold(sum);
       uint64_t a0, a1;
@@ -300,8 +386,8 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
       mac_fe(node, a0, a1, z1);
     }
   }
-  // the eight groups' shares (held by lanes 0, 8, ..., 56; zero elsewhere)
-  for (int m = 8; m < 64; m <<= 1) {
+  // the groups' shares (held by lanes 0, 16, 32, 48; zero elsewhere)
+  for (int m = GW; m < 64; m <<= 1) {
     A5 o;
 #pragma unroll
     for (int i = 0; i < 5; ++i) o.w[i] = shx64(node.w[i], m);
@@ -311,59 +397,115 @@ __device__ void node_unit(const P128Args& A, int64_t g, int lane) {
   if (lane == 0 && (uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = fold(node);
 }
 
+// Level-1 keys of the batch in LDS, a_{1,w} as four 32-bit limbs.
+__device__ __forceinline__ void stage_keys(const uint64_t* keys, uint32_t* lk) {
+  for (int i = (int)threadIdx.x; i < BLOCK; i += (int)blockDim.x) {
+    const uint64_t lo = keys[2 * i], hi = keys[2 * i + 1];
+    lk[4 * i] = (uint32_t)lo;
+    lk[4 * i + 1] = (uint32_t)(lo >> 32);
+    lk[4 * i + 2] = (uint32_t)hi;
+    lk[4 * i + 3] = (uint32_t)(hi >> 32);
+  }
+  __syncthreads();
+}
+
 // Persistent waves over the units (their number is start[count]).
 __global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lk[4 * BLOCK];
+  stage_keys(A.keys, lk);
   const int lane = (int)(threadIdx.x & 63u);
   const int64_t units = A.start[A.count];
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
-  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw) node_unit(A, g, lane);
+  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw)
+    node_unit(A, lk, g, lane);
 }
 
-// Strings of one block (at most 127 data words), SL lanes per string: lane
-// j sums words j, j + SL, ...; the partial sums are added over the lanes,
-// folded and stored (the root is level 1). A word wholly inside the string
-// is read with plain loads of the aligned dwords holding it (the one past it
-// only when misaligned); the word holding the pad is formed with guarded
-// reads.
-constexpr int SL = 2;
+// Strings of one block (at most 127 data words), four lanes per string:
+// lane j holds words j, j + 4, ..., four at a time, read at once through a
+// buffer resource over the wave's sixteen strings' bytes (range-checked per
+// dword: past the buffer's last dword the reads are zeros) and masked to
+// the padded string (Sec. 4); the four sums are added, folded and stored
+// (the root is level 1). A wave whose strings span 2 GiB or more (a long
+// string between them) reads word by word with guarded loads instead.
+constexpr int SG = 4;   // lanes per short string
+constexpr int SWL = 4;  // words per lane and round
 __global__ __launch_bounds__(256) void p128_short(P128Args A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lk[4 * BLOCK];
+  stage_keys(A.keys, lk);
+  const int lane = (int)(threadIdx.x & 63u);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = t / SL;
-  const int j = (int)(t % SL);
+  const int64_t s = t / SG;
+  const int j = (int)(t % SG);
   const bool act = s < A.count;
   const int64_t len = act ? str_len(A.off, s, A.buf_bytes) : 0;
   const bool mine = act && blocks_of(len) == 1;
+  const int64_t o0 = len ? A.off[s] : 0;
+  const uint8_t* str = A.buf + o0;
+  const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
+  const int64_t nw = mine ? len / W16 + 1 : 0;  // words, the pad's included
+  // the wave's window: from its first string's dword to the buffer's end
+  const uint64_t lo4 = (uint64_t)(uintptr_t)A.buf & ~3ull;
+  const uint64_t hi4 = ((uint64_t)(uintptr_t)A.buf + A.buf_bytes + 3) & ~3ull;
+  uint64_t wlo = mine ? (uint64_t)(uintptr_t)str - sh : ~0ull;
+  uint64_t whi = mine ? (uint64_t)(uintptr_t)str - sh + 16 * (uint64_t)nw + 4 : 0ull;
+  for (int m = 1; m < 64; m <<= 1) {
+    const uint64_t a = (uint64_t)__shfl_xor((long long)wlo, m, 64), b = (uint64_t)__shfl_xor((long long)whi, m, 64);
+    wlo = a < wlo ? a : wlo;
+    whi = b > whi ? b : whi;
+  }
+  wlo = uni64(wlo < lo4 ? lo4 : wlo);
+  whi = uni64(whi);
+  const bool windowed = whi <= wlo || whi - wlo < 0x7fffffffull;
   A5 sum;
   zero(sum);
-  if (mine) {
-    const uint8_t* str = A.buf + (len ? A.off[s] : 0);
-    const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
-    const int64_t nw = len / W16 + 1;  // words, the pad's included
-    for (int64_t w = j; w < nw; w += SL) {
-      uint64_t x0, x1, a0, a1;
-      if (W16 * w + W16 <= len) {
-        const uint64_t a4 = (uint64_t)(uintptr_t)(str + W16 * w) - sh;
-        const Q q = load16(gp16(a4));
-        const uint32_t d4 = sh ? *(const uint32_t*)gp16(a4 + 16) : 0u;
-        const uint32_t d[5] = {q.d[0], q.d[1], q.d[2], q.d[3], d4};
-        uint32_t x[4];
+  if (windowed) {
+    const uint64_t nrec = hi4 > wlo ? (hi4 - wlo < 0x7fffffffull ? hi4 - wlo : 0x7fffffffull) : 0;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)wlo, (short)0, (int)nrec, 0x00020000);
+    const uint32_t sbase = mine ? (uint32_t)((uint64_t)(uintptr_t)str - sh - wlo) : 0u;
+    int64_t rounds = (nw + SG * SWL - 1) / (SG * SWL);
+    for (int m = 1; m < 64; m <<= 1) {
+      const int64_t o = __shfl_xor((long long)rounds, m, 64);
+      rounds = o > rounds ? o : rounds;
+    }
+    for (int64_t r0 = 0; r0 < rounds; ++r0) {
+      uint32_t d[SWL][5];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
-        x0 = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
-        x1 = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
-      } else {
-        word128(str, len, w, A.buf, A.buf + A.buf_bytes, &x0, &x1);
+      for (int q = 0; q < SWL; ++q) {
+        const int64_t w = r0 * SG * SWL + j + SG * q;
+        const uint32_t o = w < nw ? sbase + 16u * (uint32_t)w : OUTSIDE;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
+        d[q][0] = v[0];
+        d[q][1] = v[1];
+        d[q][2] = v[2];
+        d[q][3] = v[3];
+        d[q][4] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 16u, 0, 0);
       }
+      __builtin_amdgcn_sched_barrier(0);
+      D7 acc;
+      zero(acc);
+#pragma unroll
+      for (int q = 0; q < SWL; ++q) {
+        const int64_t w = r0 * SG * SWL + j + SG * q;
+        uint32_t x[4];
+        word_dwords(d[q], sh, true, w < nw ? len - W16 * w : -64, x);
+        const uint4 kv = *(const uint4*)(lk + 4 * (w < BLOCK ? w : 0));
+        const uint32_t a[4] = {kv.x, kv.y, kv.z, kv.w};
+        mac128(acc, a, x);
+      }
+      add(sum, collapse(acc));
+    }
+  } else if (mine) {
+    for (int64_t w = j; w < nw; w += SG) {
+      uint64_t x0, x1, a0, a1;
+      word128(str, len, w, A.buf, A.buf + A.buf_bytes, &x0, &x1);
       key_a(A.keys, 1, (uint32_t)w, &a0, &a1);
       mac(sum, a0, a1, x0, x1);
     }
   }
-  for (int m = 1; m < SL; m <<= 1) {  // every lane takes part in the shuffles
-    A5 o;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) o.w[i] = shx64(sum.w[i], m);
-    add(sum, o);
-  }
+  // the four lanes' sums (every lane takes part in the moves)
+  add(sum, dpp5<0xB1>(sum));
+  add(sum, dpp5<0x4E>(sum));
   if (mine && j == 0) {
     add_b(sum, A.keys, 1);
     store128(A.out, A.flags, s, fold(sum));
@@ -470,7 +612,7 @@ hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* o
   P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, start, z2, units_bound};
   // persistent grids: at most 8192 waves, fewer when the units are fewer
   const int64_t waves = units_bound < 8192 ? (int64_t)units_bound : 8192;
-  hipLaunchKernelGGL(p128_short, dim3(grid_for(count * SL)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(p128_short, dim3(grid_for(count * SG)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_nodes, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_upper, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   return hipGetLastError();
