@@ -123,7 +123,12 @@ int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wav
  * Sec. 5 output, Sec. 7 mixer).
  *
  *   d_buf      device, concatenated string bytes; no alignment required
- *   buf_bytes  number of readable bytes at d_buf (loads never go past it)
+ *   buf_bytes  number of bytes at d_buf that hold the strings. The kernels
+ *              read no other byte, except that the short-string path loads
+ *              whole 16-byte-aligned granules: up to 15 bytes before a
+ *              string and after it, within the granule of one of its bytes
+ *              (a granule never crosses a page, so these loads cannot fault;
+ *              bytes outside the strings never reach an output)
  *   d_offsets  device, int64[count + 1]: string i is
  *              d_buf[d_offsets[i] .. d_offsets[i+1]); offsets must be
  *              non-decreasing and lie in [0, buf_bytes]; empty strings are
