@@ -38,27 +38,31 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 }
 __device__ __forceinline__ int64_t uni64s(int64_t v) { return (int64_t)uni64((uint64_t)v); }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-  for (int m = 1; m < 64; m <<= 1) {
-    uint32_t t = shx(v, m);
-    v = t > v ? t : v;
-  }
-  return uni(v);
+// Inclusive prefix over the wave with DPP moves only (no LDS): steps of
+// 1, 2, 4 and 8 lanes within each row of 16, then the last lane of row 0
+// into row 1 and of row 2 into row 3 (row_bcast:15), then the last lane of
+// row 1 into rows 2 and 3 (row_bcast:31). OP: 0 sum, 1 max.
+template <int OP>
+__device__ __forceinline__ uint32_t wave_incl(uint32_t v) {
+  auto op = [](uint32_t a, uint32_t b) { return OP == 0 ? a + b : (a > b ? a : b); };
+  uint32_t x = v;
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true));  // row_shr:1
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true));  // row_shr:2
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true));  // row_shr:4
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true));  // row_shr:8
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return x;
 }
-// exclusive prefix sum over the wave; *total receives the sum (uniform)
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl<1>(v), 63);
+}
+// exclusive prefix sum over the wave of values whose total stays below
+// 2^32; *total receives the sum (uniform)
 __device__ __forceinline__ uint64_t wave_excl_scan(uint64_t v, uint64_t* total) {
-  const int lane = lane_id();
-  uint64_t x = v;
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
-    uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
-    uint64_t y = ((uint64_t)hi << 32) | lo;
-    if (lane >= d) x += y;
-  }
-  uint32_t tlo = (uint32_t)__shfl((int)(uint32_t)x, 63, 64);
-  uint32_t thi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), 63, 64);
-  *total = uni64(((uint64_t)thi << 32) | tlo);
-  return x - v;
+  const uint32_t x = wave_incl<0>((uint32_t)v);
+  *total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+  return x - (uint32_t)v;
 }
 
 // ---------------------------------------------------------------------------
