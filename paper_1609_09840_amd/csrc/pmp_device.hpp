@@ -35,6 +35,33 @@ __device__ __forceinline__ void mac_sv(uint64_t& acc, uint32_t& cnt, uint32_t a,
   asm("v_addc_co_u32_e64 %0, %1, 0, %0, %2" : "+v"(cnt), "=s"(d) : "s"(c));
 }
 
+// Four sums of that form, word u of a 16-byte group going to sum u. The four
+// multiply-adds are issued before their carry adds, each carry in its own
+// register pair: a carry read right after it is written holds the wave up,
+// and four independent sums keep the multiply-adds from waiting on each other.
+struct Acc4 {
+  uint64_t lo[4];
+  uint32_t hi[4];
+};
+__device__ __forceinline__ void zero(Acc4& s) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    s.lo[u] = 0;
+    s.hi[u] = 0;
+  }
+}
+__device__ __forceinline__ void mac4(Acc4& s, const uint32_t (&a)[4], const uint32_t (&x)[4]) {
+  uint64_t k0, k1, k2, k3;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.lo[0]), "=s"(k0) : "v"(a[0]), "v"(x[0]));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.lo[1]), "=s"(k1) : "v"(a[1]), "v"(x[1]));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.lo[2]), "=s"(k2) : "v"(a[2]), "v"(x[2]));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.lo[3]), "=s"(k3) : "v"(a[3]), "v"(x[3]));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.hi[0]), "+s"(k0));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.hi[1]), "+s"(k1));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.hi[2]), "+s"(k2));
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.hi[3]), "+s"(k3));
+}
+
 // ---------------------------------------------------------------------------
 // Block sums.
 // PM+32: S = lo + 2^64 * hi  (a block sum is below 129 * 2^64)
@@ -70,6 +97,11 @@ __device__ __forceinline__ void add(S64& s, const S64& t) {
   s.w1 = (uint64_t)b;
   s.w2 = s.w2 + t.w2 + (uint32_t)(b >> 64);
 }
+// the exact total of four sums (each below 129 * 2^64 in a block sum)
+__device__ __forceinline__ S32 sum4(const Acc4& q) {
+  const u128 t = (u128)q.lo[0] + q.lo[1] + q.lo[2] + q.lo[3];
+  return S32{(uint64_t)t, q.hi[0] + q.hi[1] + q.hi[2] + q.hi[3] + (uint32_t)(t >> 64)};
+}
 __device__ __forceinline__ void add_word(S32& s, uint64_t b) {
   uint64_t lo = s.lo + b;
   s.hi += (lo < s.lo ? 1u : 0u);
@@ -99,13 +131,7 @@ __device__ __forceinline__ void mac64_vv(P64& s, uint64_t a, uint32_t x0, uint32
   asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.c2), "+s"(k2));
   asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.c1), "+s"(k3));
 }
-__device__ __forceinline__ void mac64_sv(P64& s, uint64_t a, uint32_t x0, uint32_t x1) {
-  uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  mac_sv(s.p0, s.c0, a0, x0);
-  mac_sv(s.p1, s.c1, a0, x1);
-  mac_sv(s.p1, s.c1, a1, x0);
-  mac_sv(s.p2, s.c2, a1, x1);
-}
+
 // collapse the partial sums into three words
 __device__ __forceinline__ S64 collapse(const P64& s) {
   u128 lo = (u128)s.p0 + ((u128)s.p1 << 32);  // p0 + 2^32 p1, below 2^97

@@ -103,7 +103,7 @@ __device__ __forceinline__ void group_words(const uint32_t* d, uint32_t sh, int6
 // their loads in one batch; "medium" strings (the rest of those with at most
 // MEDIUM_BLOCKS blocks, wholly in this wave's share) one per G-lane group;
 // longer strings, or strings cut by the share's ends, by the whole wave.
-constexpr uint32_t TINY_GROUPS = 16;
+constexpr uint32_t TINY_GROUPS = 17;  // strings of up to 271 bytes
 constexpr int64_t MEDIUM_BLOCKS = 32;
 static_assert(MEDIUM_BLOCKS <= BLOCK, "a medium string is one level-2 node");
 
@@ -146,6 +146,27 @@ __device__ __forceinline__ const uint8_t* gaddr(uint64_t a) {
   return (const uint8_t*)(const __attribute__((address_space(1))) uint8_t*)(uintptr_t)a;
 }
 
+// Software pipelining over `steps` steps with D buffers: the loads of step
+// n + D - 1 are issued (fill) before step n is used, so that D - 1 steps are
+// in flight while one is computed. The buffers are used in turn by a loop
+// unrolled D times, so that none is ever copied (a copy costs a move per
+// register and waits for its loads). fill may be called for steps past the
+// last; it must then read harmless memory.
+template <int D, typename Buf, typename Fill, typename Use>
+__device__ __forceinline__ void pipelined(uint32_t steps, Fill fill, Use use) {
+  Buf b[D];
+#pragma unroll
+  for (int q = 0; q + 1 < D; ++q) fill(b[q], (uint32_t)q);
+  for (uint32_t st = 0; st < steps; st += D) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      fill(b[(q + D - 1) % D], st + (uint32_t)(q + D - 1));
+      use(b[q], st + (uint32_t)q);
+      if (st + (uint32_t)q + 1 >= steps) return;
+    }
+  }
+}
+
 template <bool WIDE>
 __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table, int64_t i,
                               bool act, int64_t o0, int64_t len) {
@@ -158,7 +179,7 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
   const uint32_t lead = (uint32_t)((uintptr_t)s & 15u);
   const uint64_t a16 = (uint64_t)(uintptr_t)(s - lead);
   const uint32_t sh = lead & 3u;
-  const uint32_t ulen = act ? (uint32_t)len : 0u;  // < 256 here
+  const uint32_t ulen = act ? (uint32_t)len : 0u;  // < 272 here
   const uint32_t pbytes = act ? (ulen / W + 1) * W : 0u;  // padded length
   // chunks [a16, a16 + 16 nl) hold the string (none for an empty one: its
   // buffer may be empty); ns slots leave room for the pad word
@@ -235,38 +256,44 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
     }
     const uint32_t maxg = wave_max(in ? (pbytes + 15) / 16 : 0u);
     const uint32_t p0 = in ? r0 + (lead & ~3u) : 0u;
-    typename T::Sum acc;
+    Acc4 acc;
     zero(acc);
     P64 p;
     zero(p);
     constexpr int KPG = WIDE ? 2 : 4;  // keys per group
     const uint32_t ng = in ? (pbytes + 15) / 16 : 0u;  // this lane's groups
-    for (uint32_t g = 0; g < maxg; ++g) {
-      if (g >= ng) continue;  // lanes past their string's end sit out
-      const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
+    // a group's LDS reads are issued before the group ahead of it is summed
+    // (reads past a lane's string stay in its slots or the stage's slack)
+    struct Grp {
       uint32_t d[5];
-      uint64_t kk[KPG];
+      uint64_t k[KPG];
+    };
+    pipelined<2, Grp>(
+        maxg,
+        [&](Grp& r, uint32_t g) {
+          const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
 #pragma unroll
-      for (int u = 0; u < 5; ++u) d[u] = q[u];
+          for (int u = 0; u < 5; ++u) r.d[u] = q[u];
 #pragma unroll
-      for (int u = 0; u < KPG; ++u) kk[u] = lk[KPG * g + u];  // level-1 keys, staged in LDS
-      // every LDS read of the group is issued before its arithmetic
-      __builtin_amdgcn_sched_barrier(0);
-      uint32_t x[4];
+          for (int u = 0; u < KPG; ++u) r.k[u] = lk[KPG * g + u];  // level-1 keys, staged in LDS
+        },
+        [&](const Grp& r, uint32_t g) {
+          if (g >= ng) return;  // lanes past their string's end sit out
+          uint32_t x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = align_bytes(d[u + 1], d[u], sh);
-      if constexpr (WIDE) {
-        mac64_sv(p, kk[0], x[0], x[1]);
-        mac64_sv(p, kk[1], x[2], x[3]);
-      } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) mac_sv(acc.lo, acc.hi, (uint32_t)kk[u], x[u]);
-      }
-    }
+          for (int u = 0; u < 4; ++u) x[u] = align_bytes(r.d[u + 1], r.d[u], sh);
+          if constexpr (WIDE) {
+            mac64_vv(p, r.k[0], x[0], x[1]);
+            mac64_vv(p, r.k[1], x[2], x[3]);
+          } else {
+            const uint32_t k[4] = {(uint32_t)r.k[0], (uint32_t)r.k[1], (uint32_t)r.k[2], (uint32_t)r.k[3]};
+            mac4(acc, k, x);
+          }
+        });
     if (in) {
       typename T::Sum tot;
       if constexpr (WIDE) tot = collapse(p);
-      else tot = acc;
+      else tot = sum4(acc);
       add_word(tot, (uint64_t)keys[8 * BLOCK]);  // b_1
       store_out<WIDE>(B, i, reduce(tot));
     }
@@ -386,6 +413,7 @@ __device__ void climb(const KArgs& A, const BatchArgs& B, int64_t i, uint64_t sb
 // the block may be inactive (act) or run past the string end (rem = string
 // bytes from the block start); its words are masked to the padded string of
 // Sec. 4.
+
 template <bool WIDE, int G>
 struct Pieces {
   static constexpr int NL = BLOCK * Tr<WIDE>::W / 16 / G;  // pieces per lane
@@ -435,8 +463,9 @@ __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G
   constexpr int NL = Pieces<WIDE, G>::NL;
   constexpr int32_t BW = BLOCK * W;
   typename T::Sum acc;
+  Acc4 q;
   P64 p;
-  zero(acc);
+  zero(q);
   zero(p);
   // string bytes from the block's start, clamped (inactive: every dword dropped)
   const int32_t rr = !TAIL ? BW : !act ? -16 : rem < -16 ? -16 : rem > BW ? BW : (int32_t)rem;
@@ -454,8 +483,8 @@ __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G
       mac64_vv(p, kp[0], x[0], x[1]);
       mac64_vv(p, kp[1], x[2], x[3]);
     } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) mac_vv(acc.lo, acc.hi, (uint32_t)kp[u], x[u]);
+      const uint32_t k[4] = {(uint32_t)kp[0], (uint32_t)kp[1], (uint32_t)kp[2], (uint32_t)kp[3]};
+      mac4(q, k, x);
     }
   }
   if constexpr (TAIL) {
@@ -468,11 +497,12 @@ __device__ __forceinline__ typename Tr<WIDE>::Sum block_sum(const Pieces<WIDE, G
         const bool high = bd & 1;
         mac64_vv(p, lk[bd >> 1], high ? 0u : v, high ? v : 0u);
       } else {
-        mac_vv(acc.lo, acc.hi, (uint32_t)lk[bd], v);
+        mac_vv(q.lo[0], q.hi[0], (uint32_t)lk[bd], v);
       }
     }
   }
   if constexpr (WIDE) acc = collapse(p);
+  else acc = sum4(q);
   return acc;
 }
 

@@ -300,9 +300,10 @@ def test_stage_overflow_passes(wide, lead):
     Wb = 8 if wide else 4
     blk = 128 * Wb
     rng = np.random.default_rng(61 + lead)
-    tiny = rng.integers(236, 256, size=300)                    # 15..16 groups of 16 bytes
+    tiny = rng.integers(250, 272, size=300)                    # 16..17 groups of 16 bytes
     med = rng.integers(15 * blk + 1, 16 * blk - Wb, size=200)  # 16 blocks each
-    mixed = np.concatenate([tiny[:100], med[:100], tiny[100:], med[100:], rng.integers(0, 16 * blk, size=300)])
+    edge = np.array([271, 272, 273, 271, 0, 272] * 20)         # the last one-lane length and the first one past it
+    mixed = np.concatenate([tiny[:100], med[:100], edge, tiny[100:], med[100:], rng.integers(0, 16 * blk, size=300)])
     from paper_1609_09840_amd import pmp
 
     plan = pmp.Plan(0)
