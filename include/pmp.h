@@ -133,7 +133,9 @@ int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wav
  *              d_buf[d_offsets[i] .. d_offsets[i+1]); offsets must be
  *              non-decreasing and lie in [0, buf_bytes]; empty strings are
  *              allowed. A string whose offsets break this gets no output and
- *              the plan's status becomes PMP_E_OFFSETS.
+ *              the plan's status becomes PMP_E_OFFSETS; since the work is
+ *              split among waves by offset, strings near offsets that
+ *              decrease may get no output either.
  *   count      number of strings (0 is a no-op)
  *   d_keys     device, key table of PMP_KEYS entries (layout above)
  *   d_out      device output:

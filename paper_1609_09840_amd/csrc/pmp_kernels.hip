@@ -113,22 +113,23 @@ static_assert(MEDIUM_BLOCKS <= BLOCK, "a medium string is one level-2 node");
 // Per-lane loads of 64 unrelated strings are slow (64 cache lines per load
 // instruction, and few in flight per lane), so the wave first copies the
 // 16-byte chunks that hold its tiny strings into its LDS stage with
-// direct-to-LDS loads. Each lane reserves slots c0 .. c0 + ns - 1 of the
-// stage in lane order (its chunks plus room for the pad word) and writes the
-// numbers of its chunks, relative to the first string's chunk, into a slot
-// table; load instruction k then fills slots 64k .. 64k + 63, and since
-// consecutive slots mostly belong to one string the loads are coalesced.
-// Lanes that do not fit go in a further pass. Each lane then writes the pad
-// (Sec. 4: a byte 0x01, zeros to the end of its slots) into its own copy, so
-// that the words of its padded string read straight out of the stage; its
-// slots cover every group it reads, so the words past the padded end read as
-// zero, and a lane sits out the groups past its string's end. The group's keys are
-// wave-uniform LDS reads (broadcast) and the products are summed exactly with
-// v_mad_u64_u32 plus a carry counter (one fold per string).
+// direct-to-LDS loads. The strings of a tile lie back to back in the buffer:
+// when the chunks from the first one's to the last one's fit in the stage,
+// they are copied as one run (64 consecutive chunks per load). Otherwise each
+// lane reserves slots c0 .. c0 + nl - 1 of the stage in lane order (one per
+// chunk of its string) and writes the numbers of its chunks, relative to the
+// first string's chunk, into a slot table; load instruction k then fills
+// slots 64k .. 64k + 63, and since consecutive slots mostly belong to one
+// string those loads are coalesced too. Lanes that do not fit go in a further
+// pass. Each lane then sums the words of its string straight out of the
+// stage: every group but the last is wholly inside the string; the last one,
+// which holds the end, is masked to the padded string (Sec. 4: the bytes, a
+// byte 0x01, zeros) in registers. The keys of a group are wave-uniform LDS
+// reads (broadcast) and the products are summed exactly with v_mad_u64_u32
+// plus carry counters (one fold per string).
 constexpr uint32_t STAGE_CHUNKS = 768;             // 12 KiB of string bytes per wave
 constexpr uint32_t STAGE_BYTES = 16 * STAGE_CHUNKS;
-constexpr uint32_t STAGE_SLACK = 512;              // reads past a lane's slots stay in the wave's region
-constexpr uint32_t NO_CHUNK = ~0u;
+constexpr uint32_t STAGE_SLACK = 512;              // reads past a lane's chunks stay in the wave's region
 
 // s_waitcnt through the builtin, so that the compiler's own wait insertion
 // knows that every outstanding load (direct-to-LDS ones included) is done.
@@ -167,6 +168,84 @@ __device__ __forceinline__ void pipelined(uint32_t steps, Fill fill, Use use) {
   }
 }
 
+// Dword u (string bytes 4u .. 4u + 3 from the group's start) of the group
+// holding a string's end, rem = string bytes from the group's start: kept
+// whole, cut at the end with the pad byte 0x01 after it, or zero (Sec. 4).
+__device__ __forceinline__ uint32_t tail_dword(uint32_t x, int32_t r) {
+  if (r >= 4) return x;
+  if (r < 0) return 0u;
+  const uint32_t b = 8u * (uint32_t)r;
+  return (x & ((1u << b) - 1u)) | (1u << b);
+}
+
+// The sums of the tiny strings of the lanes in `in`, whose padded strings
+// start p0 bytes into the stage (4-aligned, sh bytes before the string),
+// once their chunks have been copied: b_1 + sum of key times word, folded.
+template <bool WIDE>
+__device__ __forceinline__ void hash_staged(const BatchArgs& B, const uint64_t* lk, const uint8_t* stage, int64_t i,
+                                            bool in, uint32_t p0, uint32_t sh, uint32_t ulen, uint32_t ng) {
+  using T = Tr<WIDE>;
+  constexpr int KPG = WIDE ? 2 : 4;  // keys per group
+  wait_vm0();
+  const uint32_t maxg = wave_max(in ? ng : 0u);
+  Acc4 acc;
+  zero(acc);
+  P64 p;
+  zero(p);
+  auto mac = [&](const uint32_t (&x)[4], const uint64_t (&k)[KPG]) {
+    if constexpr (WIDE) {
+      mac64_vv(p, k[0], x[0], x[1]);
+      mac64_vv(p, k[1], x[2], x[3]);
+    } else {
+      const uint32_t k32[4] = {(uint32_t)k[0], (uint32_t)k[1], (uint32_t)k[2], (uint32_t)k[3]};
+      mac4(acc, k32, x);
+    }
+  };
+  // every group but the last: a group's LDS reads are issued before the one
+  // ahead of it is summed (reads past a lane's string stay in the stage or its
+  // slack; lanes past their full groups sit out)
+  struct Grp {
+    uint32_t d[5];
+    uint64_t k[KPG];
+  };
+  pipelined<2, Grp>(
+      maxg > 0 ? maxg - 1 : 0u,
+      [&](Grp& r, uint32_t g) {
+        const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
+#pragma unroll
+        for (int u = 0; u < 5; ++u) r.d[u] = q[u];
+#pragma unroll
+        for (int u = 0; u < KPG; ++u) r.k[u] = lk[KPG * g + u];  // level-1 keys, staged in LDS
+      },
+      [&](const Grp& r, uint32_t g) {
+        if (g + 1 >= ng) return;
+        uint32_t x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = align_bytes(r.d[u + 1], r.d[u], sh);
+        mac(x, r.k);
+      });
+  if (!in) return;
+  // the last group, masked to the padded string
+  const uint32_t gl = ng - 1;
+  const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * gl);
+  uint32_t d[5];
+  uint64_t k[KPG];
+#pragma unroll
+  for (int u = 0; u < 5; ++u) d[u] = q[u];
+#pragma unroll
+  for (int u = 0; u < KPG; ++u) k[u] = lk[KPG * gl + u];
+  const int32_t rem = (int32_t)ulen - 16 * (int32_t)gl;
+  uint32_t x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) x[u] = tail_dword(align_bytes(d[u + 1], d[u], sh), rem - 4 * u);
+  mac(x, k);
+  typename T::Sum tot;
+  if constexpr (WIDE) tot = collapse(p);
+  else tot = sum4(acc);
+  add_word(tot, (uint64_t)((const typename T::key_t*)B.keys)[8 * BLOCK]);  // b_1
+  store_out<WIDE>(B, i, reduce(tot));
+}
+
 template <bool WIDE>
 __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table, int64_t i,
                               bool act, int64_t o0, int64_t len) {
@@ -180,47 +259,60 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
   const uint64_t a16 = (uint64_t)(uintptr_t)(s - lead);
   const uint32_t sh = lead & 3u;
   const uint32_t ulen = act ? (uint32_t)len : 0u;  // < 272 here
-  const uint32_t pbytes = act ? (ulen / W + 1) * W : 0u;  // padded length
+  const uint32_t ng = act ? ((ulen / W + 1) * W + 15) / 16 : 0u;  // groups of the padded string
   // chunks [a16, a16 + 16 nl) hold the string (none for an empty one: its
-  // buffer may be empty); ns slots leave room for the pad word
+  // buffer may be empty)
   const uint32_t nl = act && ulen > 0 ? (lead + ulen + 15) / 16 : 0u;
-  // (and every group the lane reads, 4 bytes past the last one included:
-  // the stage is zero from the pad to the end of the slots, so the words past
-  // the padded string read as zero and need no mask)
-  const uint32_t ns0 = act ? (lead + ulen + W + 15) / 16 : 0u;
-  const uint32_t ns1 = act ? ((lead & ~3u) + 16 * ((pbytes + 15) / 16) + 4 + 15) / 16 : 0u;
-  const uint32_t ns = ns0 > ns1 ? ns0 : ns1;
-  uint64_t total = 0;
-  const uint32_t c0 = (uint32_t)wave_excl_scan(ns, &total);
-  const typename T::key_t* __restrict__ keys = (const typename T::key_t*)B.keys;
   const auto* lds1 = (__attribute__((address_space(3))) uint8_t*)stage;
+  auto rl64 = [](uint64_t v, int l) {
+    return uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l)) |
+                 ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32));
+  };
+  {
+    // one run of chunks, from the first string's to the end of the last one's
+    const uint64_t tb = rl64(a16, __ffsll((unsigned long long)todo) - 1);
+    const uint64_t rend = act ? ((a16 - tb) >> 4) + nl : 0;  // (huge when a16 < tb)
+    const uint32_t tp = wave_max(rend < STAGE_CHUNKS ? (uint32_t)rend : STAGE_CHUNKS + 1);
+    if (!__ballot(act && a16 < tb) && tp <= STAGE_CHUNKS) {
+      wait_lgkm0();  // the stage's previous readers are done
+      for (uint32_t k = 0; 64 * k < tp; ++k) {
+        const uint32_t j = 64 * k + (uint32_t)lane;
+        if (j < tp)
+          __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)(tb + 16ull * j),
+                                           (__attribute__((address_space(3))) void*)(lds1 + 1024 * k), 16, 0, 0);
+      }
+      hash_staged<WIDE>(B, lk, stage, i, act, act ? (uint32_t)(a16 - tb) + (lead & ~3u) : 0u, sh, ulen, ng);
+      return;
+    }
+  }
+  uint64_t total = 0;
+  const uint32_t c0 = (uint32_t)wave_excl_scan(nl, &total);
   uint32_t base = 0;  // first slot number of this pass
   while (todo) {
     const bool mine = (todo >> lane) & 1ull;
     // chunk numbers are kept relative to the pass's first string, in 32 bits
-    const int first = __ffsll((unsigned long long)todo) - 1;
-    const uint64_t tb = uni64(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a16, first)) |
-                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a16 >> 32), first) << 32));
+    const uint64_t tb = rl64(a16, __ffsll((unsigned long long)todo) - 1);
     const uint64_t rel = (a16 - tb) >> 4;
-    const bool in = mine && c0 + ns - base <= STAGE_CHUNKS && rel + nl < (1ull << 32);
+    const bool fits = c0 + nl - base <= STAGE_CHUNKS && rel + nl < (1ull << 32);
+    // the pass takes its lanes up to the first one that does not fit, so
+    // that every slot below tp is written (the first lane always fits: it
+    // holds at most TINY_GROUPS + 2 chunks at rel = 0); offsets that decrease
+    // somewhere can leave a later string in front of the first one
+    const uint64_t stop = __ballot(mine && !fits);
+    const bool in = mine && fits && (stop == 0 || lane < __ffsll((unsigned long long)stop) - 1);
     const uint64_t pm = __ballot(in);
-    const uint32_t tp = wave_max(in ? c0 + ns - base : 0u);  // slots used by this pass
+    const uint32_t tp = wave_max(in ? c0 + nl - base : 0u);  // slots used by this pass
     wait_lgkm0();  // the previous pass is done reading the stage
     // (also written with inline asm, so that the compiler does not wait for
     // the previous tile's output stores before each entry)
     if (in) {
       const uint32_t ta = lds_addr(table) + 4 * (c0 - base);
       // two entries per write
-      for (uint32_t t = 0; t + 1 < ns; t += 2) {
-        const uint32_t v0 = t < nl ? (uint32_t)rel + t : NO_CHUNK;
-        const uint32_t v1 = t + 1 < nl ? (uint32_t)rel + t + 1 : NO_CHUNK;
-        asm volatile("ds_write2_b32 %0, %1, %2 offset1:1" ::"v"(ta + 4 * t), "v"(v0), "v"(v1) : "memory");
-      }
-      if (ns & 1u) {
-        const uint32_t t = ns - 1;
-        const uint32_t v = t < nl ? (uint32_t)rel + t : NO_CHUNK;
-        asm volatile("ds_write_b32 %0, %1" ::"v"(ta + 4 * t), "v"(v) : "memory");
-      }
+      for (uint32_t t = 0; t + 1 < nl; t += 2)
+        asm volatile("ds_write2_b32 %0, %1, %2 offset1:1" ::"v"(ta + 4 * t), "v"((uint32_t)rel + t),
+                     "v"((uint32_t)rel + t + 1)
+                     : "memory");
+      if (nl & 1u) asm volatile("ds_write_b32 %0, %1" ::"v"(ta + 4 * (nl - 1)), "v"((uint32_t)rel + nl - 1) : "memory");
     }
     // Four table entries per read: the table is read with inline asm (its
     // wait included) because the compiler would otherwise wait for every
@@ -239,64 +331,12 @@ __device__ void short_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* s
         const uint32_t k = k0 + u;
         if (k * 64 >= tp) break;  // uniform
         const uint32_t j = k * 64 + (uint32_t)lane;
-        if (j < tp && e[u] != NO_CHUNK)
+        if (j < tp)
           __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)(tb + 16ull * e[u]),
                                            (__attribute__((address_space(3))) void*)(lds1 + 1024 * k), 16, 0, 0);
       }
     }
-    wait_vm0();
-    // the pad in this lane's own slots: 0x01 after the string, zeros to the end
-    const uint32_t r0 = 16 * (c0 - base);  // this lane's first slot, in bytes
-    if (in) {
-      const uint32_t z0 = r0 + lead + ulen, zw = z0 & ~3u, zb = 8 * (z0 & 3u);
-      uint32_t* dw = (uint32_t*)(stage + zw);
-      const uint32_t keep = zb ? (dw[0] & ((1u << zb) - 1u)) : 0u;
-      dw[0] = keep | (1u << zb);
-      for (uint32_t q = zw + 4; q < r0 + 16 * ns; q += 4) *(uint32_t*)(stage + q) = 0u;
-    }
-    const uint32_t maxg = wave_max(in ? (pbytes + 15) / 16 : 0u);
-    const uint32_t p0 = in ? r0 + (lead & ~3u) : 0u;
-    Acc4 acc;
-    zero(acc);
-    P64 p;
-    zero(p);
-    constexpr int KPG = WIDE ? 2 : 4;  // keys per group
-    const uint32_t ng = in ? (pbytes + 15) / 16 : 0u;  // this lane's groups
-    // a group's LDS reads are issued before the group ahead of it is summed
-    // (reads past a lane's string stay in its slots or the stage's slack)
-    struct Grp {
-      uint32_t d[5];
-      uint64_t k[KPG];
-    };
-    pipelined<2, Grp>(
-        maxg,
-        [&](Grp& r, uint32_t g) {
-          const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * g);
-#pragma unroll
-          for (int u = 0; u < 5; ++u) r.d[u] = q[u];
-#pragma unroll
-          for (int u = 0; u < KPG; ++u) r.k[u] = lk[KPG * g + u];  // level-1 keys, staged in LDS
-        },
-        [&](const Grp& r, uint32_t g) {
-          if (g >= ng) return;  // lanes past their string's end sit out
-          uint32_t x[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = align_bytes(r.d[u + 1], r.d[u], sh);
-          if constexpr (WIDE) {
-            mac64_vv(p, r.k[0], x[0], x[1]);
-            mac64_vv(p, r.k[1], x[2], x[3]);
-          } else {
-            const uint32_t k[4] = {(uint32_t)r.k[0], (uint32_t)r.k[1], (uint32_t)r.k[2], (uint32_t)r.k[3]};
-            mac4(acc, k, x);
-          }
-        });
-    if (in) {
-      typename T::Sum tot;
-      if constexpr (WIDE) tot = collapse(p);
-      else tot = sum4(acc);
-      add_word(tot, (uint64_t)keys[8 * BLOCK]);  // b_1
-      store_out<WIDE>(B, i, reduce(tot));
-    }
+    hash_staged<WIDE>(B, lk, stage, i, in, in ? 16 * (c0 - base) + (lead & ~3u) : 0u, sh, ulen, ng);
     todo &= ~pm;
     base += tp;
   }

@@ -203,6 +203,38 @@ def test_bad_offsets_reported():
     plan.close()
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_bad_offsets_string_before_the_first(wide):
+    """A string that runs backwards lets the next string start in front of
+    the first one of its tile, with short strings after it. With the whole
+    batch in one wave's share, every string with valid offsets still hashes
+    (the one-lane strings of the tile are then copied chunk by chunk, in
+    passes that stop at the first string that does not fit)."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(87)
+    buf = rng.integers(0, 256, size=4096, dtype=np.uint8)
+    offs = np.array([200, 300, 0, 250, 260, 270, 280, 290, 300] + list(range(310, 3000, 37)), dtype=np.int64)
+    say(f"case bad-offsets-in-front: wide={wide} count={len(offs) - 1}")
+    plan = pmp.Plan(0)
+    plan.tune(0, 0, 1 << 26, 1)  # one wave: its share is the whole batch
+    keys_np = U.keys_for(wide, 88)
+    fn = pmp.pmp_hash64 if wide else pmp.pmp_hash32
+    out = fn(torch.from_numpy(buf).to(U.dev()), torch.from_numpy(offs).to(U.dev()), U.to_dev_keys(keys_np), flags=0,
+             plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == pmp.PMP_E_OFFSETS
+    got = U.as_u64(out.cpu().numpy())  # one output word per string
+    for k in range(len(offs) - 1):
+        if offs[k] > offs[k + 1]:
+            continue
+        want = U.oracle_hash(W.Ragged(buf, offs[k:k + 2].copy(), wide), keys_np, 0)
+        assert got[k] == want[0], k
+    plan.close()
+
+
 TILE_PAIRS = [(8, 16), (8, 8), (16, 16), (4, 16), (16, 8), (4, 8)]
 
 
