@@ -247,22 +247,37 @@ __device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
 // diagonals d = i + j of (sum a_i x_j) 2^(32 d); diagonal d is kept as
 // acc[d] + 2^64 cnt[d] (v_mad_u64_u32 with its carry counted), and turned
 // into five 64-bit limbs once per block.
-struct D7 {
-  uint64_t acc[7];
-  uint32_t cnt[7];
+template <int ND>
+struct Dg {
+  uint64_t acc[ND];
+  uint32_t cnt[ND];
 };
-__device__ __forceinline__ void zero(D7& s) {
+using D7 = Dg<7>;  // a 128 x 128 product sum
+template <int ND>
+__device__ __forceinline__ void zero(Dg<ND>& s) {
 #pragma unroll
-  for (int d = 0; d < 7; ++d) {
+  for (int d = 0; d < ND; ++d) {
     s.acc[d] = 0;
     s.cnt[d] = 0;
   }
 }
-__device__ __forceinline__ void mac128(D7& s, const uint32_t* a, const uint32_t* x) {
+// (for each limb a_i the four multiply-adds, on four different diagonals,
+// are issued before their four carry adds: a carry read right after it is
+// written holds the wave up)
+template <int ND>
+__device__ __forceinline__ void mac128(Dg<ND>& s, const uint32_t* a, const uint32_t* x) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) mac_vv(s.acc[i + j], s.cnt[i + j], a[i], x[j]);
+  for (int i = 0; i < 4; ++i) {
+    uint64_t k0, k1, k2, k3;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.acc[i]), "=s"(k0) : "v"(a[i]), "v"(x[0]));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.acc[i + 1]), "=s"(k1) : "v"(a[i]), "v"(x[1]));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.acc[i + 2]), "=s"(k2) : "v"(a[i]), "v"(x[2]));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(s.acc[i + 3]), "=s"(k3) : "v"(a[i]), "v"(x[3]));
+    asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.cnt[i]), "+s"(k0));
+    asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.cnt[i + 1]), "+s"(k1));
+    asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.cnt[i + 2]), "+s"(k2));
+    asm("v_addc_co_u32_e64 %0, %1, 0, %0, %1" : "+v"(s.cnt[i + 3]), "+s"(k3));
+  }
 }
 // s += v at 64-bit limb k (k <= 4), carries up to limb 4
 __device__ __forceinline__ void add_limb(A5& s, uint64_t v, int k) {
@@ -275,11 +290,13 @@ __device__ __forceinline__ void add_limb(A5& s, uint64_t v, int k) {
     s.w[i] = t;
   }
 }
-__device__ __forceinline__ A5 collapse(const D7& s) {
+// the diagonals as five 64-bit limbs (the sum must lie below 2^320)
+template <int ND>
+__device__ __forceinline__ A5 collapse(const Dg<ND>& s) {
   A5 r;
   zero(r);
 #pragma unroll
-  for (int d = 0; d < 7; ++d) {
+  for (int d = 0; d < ND; ++d) {
     const int m = d >> 1;
     if ((d & 1) == 0) {
       add_limb(r, s.acc[d], m);
@@ -299,13 +316,6 @@ __device__ __forceinline__ A5 dpp5(const A5& s) {
   for (int i = 0; i < 5; ++i) r.w[i] = dpp<CTRL>(s.w[i]);
   return r;
 }
-// sum over aligned groups of 16 lanes, every lane of a group ends with it
-__device__ __forceinline__ void group16_sum(A5& s) {
-  add(s, dpp5<0xB1>(s));
-  add(s, dpp5<0x4E>(s));
-  add(s, dpp5<0x141>(s));
-  add(s, dpp5<0x140>(s));
-}
 
 constexpr uint32_t OUTSIDE = 0x80000000u;  // past every buffer resource's end
 
@@ -321,16 +331,28 @@ __device__ __forceinline__ void word_dwords(const uint32_t* d, uint32_t sh, bool
 }
 
 // Unit g: part k of string s's level-2 nodes (blocks QB k .. QB k + 31). The
-// wave takes 4 blocks at a time, 16 lanes per block: lane j of a group holds
-// words j, j + 16, ..., j + 112 of its block, all eight read at once through
+// wave takes 8 blocks at a time, 8 lanes per block: lane j of a group holds
+// words j, j + 8, ..., j + 120 of its block, all sixteen read at once through
 // a buffer resource over the unit's bytes (range-checked per dword by the
 // hardware: reads past the string's last dword are zeros, nothing is
 // fetched for them), with the level-1 keys from LDS. The group adds its
-// sixteen sums, folds, and multiplies by the block's level-2 key; the
-// unit's share of its node is reduced and stored.
-constexpr int GW = 16;              // lanes per block
+// eight sums, folds, and multiplies by the block's level-2 key; the unit's
+// share of its node is reduced and stored. (Eight lanes per block spread a
+// step's fold and level-2 product over 16 KiB; at 168 VGPRs three waves per
+// SIMD stay resident.)
+constexpr int GW = 8;               // lanes per block
 constexpr int WPL = BLOCK / GW;     // words per lane and block
 constexpr int BPS = 64 / GW;        // blocks per wave step
+constexpr int SPLIT = 1;            // load rounds per step
+constexpr int WPR = WPL / SPLIT;    // words per lane and round
+static_assert(WPL % SPLIT == 0, "whole rounds");
+// sum over aligned groups of GW lanes, every lane of a group ends with it
+__device__ __forceinline__ void group_sum(A5& s) {
+  add(s, dpp5<0xB1>(s));
+  add(s, dpp5<0x4E>(s));
+  if constexpr (GW >= 8) add(s, dpp5<0x141>(s));
+  if constexpr (GW >= 16) add(s, dpp5<0x140>(s));
+}
 __device__ void node_unit(const P128Args& A, const uint32_t* lk, int64_t g, int lane) {
   const int64_t s = unit_string(A, g, lane);
   const int64_t k = g - A.start[s];
@@ -352,32 +374,36 @@ __device__ void node_unit(const P128Args& A, const uint32_t* lk, int64_t g, int 
   for (int64_t cb = c0; cb < c1; cb += BPS) {
     const int64_t c = cb + grp;
     const bool act = c < c1;
-    uint32_t d[WPL][5];
-#pragma unroll
-    for (int t = 0; t < WPL; ++t) {
-      const uint32_t o = act ? (uint32_t)(c - c0) * (uint32_t)BLK_BYTES + 16u * (uint32_t)(j + GW * t) : OUTSIDE;
-      const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
-      d[t][0] = q[0];
-      d[t][1] = q[1];
-      d[t][2] = q[2];
-      d[t][3] = q[3];
-      d[t][4] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 16u, 0, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);  // every load of the step is issued before any is used
     const bool tail = __ballot(act && c * (int64_t)BLK_BYTES + (int64_t)BLK_BYTES > len) != 0;
     D7 acc;
     zero(acc);
 #pragma unroll
-    for (int t = 0; t < WPL; ++t) {
-      const int w = j + GW * t;
-      uint32_t x[4];
-      word_dwords(d[t], sh, tail, len - W16 * (c * BLOCK + w), x);
-      const uint4 kv = *(const uint4*)(lk + 4 * w);  // a_{1,w} as four 32-bit limbs
-      const uint32_t a[4] = {kv.x, kv.y, kv.z, kv.w};
-      mac128(acc, a, x);
+    for (int h = 0; h < SPLIT; ++h) {
+      uint32_t d[WPR][5];
+#pragma unroll
+      for (int t = 0; t < WPR; ++t) {
+        const uint32_t o =
+            act ? (uint32_t)(c - c0) * (uint32_t)BLK_BYTES + 16u * (uint32_t)(j + GW * (WPR * h + t)) : OUTSIDE;
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
+        d[t][0] = q[0];
+        d[t][1] = q[1];
+        d[t][2] = q[2];
+        d[t][3] = q[3];
+        d[t][4] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 16u, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // every load of the round is issued before any is used
+#pragma unroll
+      for (int t = 0; t < WPR; ++t) {
+        const int w = j + GW * (WPR * h + t);
+        uint32_t x[4];
+        word_dwords(d[t], sh, tail, len - W16 * (c * BLOCK + w), x);
+        const uint4 kv = *(const uint4*)(lk + 4 * w);  // a_{1,w} as four 32-bit limbs
+        const uint32_t a[4] = {kv.x, kv.y, kv.z, kv.w};
+        mac128(acc, a, x);
+      }
     }
     A5 sum = collapse(acc);
-    group16_sum(sum);
+    group_sum(sum);
     if (act && j == 0) {
       add_b(sum, A.keys, 1);
       const F128 z1 = fold(sum);
@@ -410,7 +436,7 @@ __device__ __forceinline__ void stage_keys(const uint64_t* keys, uint32_t* lk) {
 }
 
 // Persistent waves over the units (their number is start[count]).
-__global__ __launch_bounds__(256) void p128_nodes(P128Args A) {
+__global__ __launch_bounds__(256, 3) void p128_nodes(P128Args A) {
   __shared__ __attribute__((aligned(16))) uint32_t lk[4 * BLOCK];
   stage_keys(A.keys, lk);
   const int lane = (int)(threadIdx.x & 63u);
