@@ -54,7 +54,7 @@ DESCR = {
 
 
 KERNEL_SOURCES = {
-    "pmp_kernels.hip": ("pmp_kernels.hip", "pmp_device.hpp", "pmp_batch.h"),
+    "pmp_kernels.hip": ("pmp_kernels.hip", "pmp_device.hpp", "pmp_batch.h", "pmp_stage.hpp"),
     "pmp_incr.hip": ("pmp_incr.hip", "pmp_device.hpp", "pmp_batch.h", "pmp_incr.h"),
 }
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpmp.so")
 SOURCES = ["pmp_kernels.hip", "pmp_static.hip", "pmp_incr.hip", "pmp_table.hip", "pmp_pm128.hip", "pmp_probe.hip", "pmp_api.cpp", "pmp_server.cpp"]
-HEADERS = ["pmp_device.hpp", "pmp_internal.h", "pmp_batch.h", "pmp_incr.h"]
+HEADERS = ["pmp_device.hpp", "pmp_internal.h", "pmp_batch.h", "pmp_incr.h", "pmp_stage.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 BUILD_DIR = os.path.join(PKG, "_build")

@@ -20,8 +20,11 @@
 // sum a_{2,i} z_i reduced mod p, is stored; (4) one wave
 // per string of more than one block adds each node's units and b_2 and
 // climbs the levels above 2 in place.
+#include <atomic>
+
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
+#include "pmp_stage.hpp"
 
 namespace pmp {
 
@@ -126,10 +129,6 @@ __device__ F128 fold(const A5& S) {
   return z;
 }
 
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ uint64_t uni64(uint64_t v) {
-  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
-}
 
 __device__ __forceinline__ const uint8_t* gp16(uint64_t a) {
   return (const uint8_t*)(const __attribute__((address_space(1))) uint8_t*)(uintptr_t)a;
@@ -206,11 +205,6 @@ __device__ __forceinline__ void store128(void* out, uint32_t flags, int64_t i, c
   }
 }
 
-__global__ void p128_count(const int64_t* off, int64_t count, uint64_t buf_bytes, uint32_t* cnt) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    cnt[i] = (uint32_t)units_of(str_len(off, i, buf_bytes));
-}
-
 struct P128Args {
   const uint8_t* buf;
   uint64_t buf_bytes;
@@ -219,26 +213,41 @@ struct P128Args {
   const uint64_t* keys;
   void* out;
   uint32_t flags;
-  const int64_t* start;  // count + 1: first unit of each string
-  F128* z2;              // level-2 values of strings with more than one node, at start[s] + k
-  uint64_t zcap;         // entries of z2 (only offsets that decrease can ask for more)
+  uint32_t* tcnt;         // units of each tile of 64 strings
+  const int64_t* tstart;  // tiles + 1: first unit of each tile (the last entry is the total)
+  F128* z2;               // level-2 values of strings with more than one node, at start(s) + k
+  uint64_t zcap;          // entries of z2 (only offsets that decrease can ask for more)
 };
+constexpr int64_t TILE = 64;  // strings per tile
+__device__ __forceinline__ int64_t tiles_of(int64_t count) { return (count + TILE - 1) / TILE; }
 
-// The string s with start[s] <= g < start[s + 1] (strings without units
-// share their start with the next one, so the last such s): a 64-ary search
-// by the whole wave.
-__device__ int64_t unit_string(const P128Args& A, int64_t g, int lane) {
-  int64_t lo = 0, hi = A.count;
+// Unit g: part k of string s, whose first unit is start (the units of a
+// string are numbered after those of the strings before it). The tile by a
+// 64-ary search over the tile starts, then the string by a wave scan of its
+// tile's unit counts.
+struct UnitPos {
+  int64_t s, k, start;
+};
+__device__ UnitPos unit_at(const P128Args& A, int64_t g, int lane) {
+  int64_t lo = 0, hi = tiles_of(A.count);
   while (hi - lo > 1) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t idx = lo + (int64_t)lane * step;
-    const bool le = idx < hi && A.start[idx] <= g;
+    const bool le = idx < hi && A.tstart[idx] <= g;
     const uint64_t mask = __ballot(le);
     const int last = 63 - __clzll((long long)mask);
     lo = lo + (int64_t)last * step;
     hi = lo + step < hi ? lo + step : hi;
   }
-  return lo;
+  const int64_t i = lo * TILE + lane;
+  const uint32_t u = i < A.count ? (uint32_t)units_of(str_len(A.off, i, A.buf_bytes)) : 0u;
+  uint64_t tot = 0;
+  const int64_t ex = (int64_t)wave_excl_scan(u, &tot);
+  const int64_t r = g - A.tstart[lo];  // the unit's rank in its tile
+  const uint64_t own = __ballot(u > 0 && ex <= r && r < ex + (int64_t)u);
+  const int l = own ? __ffsll((unsigned long long)own) - 1 : 0;
+  const int64_t exl = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ex, l);
+  return UnitPos{lo * TILE + l, r - exl, A.tstart[lo] + exl};
 }
 
 // ---------------------------------------------------------------------------
@@ -354,8 +363,8 @@ __device__ __forceinline__ void group_sum(A5& s) {
   if constexpr (GW >= 16) add(s, dpp5<0x140>(s));
 }
 __device__ void node_unit(const P128Args& A, const uint32_t* lk, int64_t g, int lane) {
-  const int64_t s = unit_string(A, g, lane);
-  const int64_t k = g - A.start[s];
+  const UnitPos up = unit_at(A, g, lane);
+  const int64_t s = up.s, k = up.k;
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const uint8_t* str = A.buf + (len ? A.off[s] : 0);
   const int64_t n1 = blocks_of(len);
@@ -420,7 +429,7 @@ __device__ void node_unit(const P128Args& A, const uint32_t* lk, int64_t g, int 
     add(node, o);
   }
   // the unit's share of its node, reduced (b_2 is added with the node)
-  if (lane == 0 && (uint64_t)(A.start[s] + k) < A.zcap) A.z2[A.start[s] + k] = fold(node);
+  if (lane == 0 && (uint64_t)(up.start + k) < A.zcap) A.z2[up.start + k] = fold(node);
 }
 
 // Level-1 keys of the batch in LDS, a_{1,w} as four 32-bit limbs.
@@ -435,36 +444,30 @@ __device__ __forceinline__ void stage_keys(const uint64_t* keys, uint32_t* lk) {
   __syncthreads();
 }
 
-// Persistent waves over the units (their number is start[count]).
+// Persistent waves over the units (their number is the last tile start).
 __global__ __launch_bounds__(256, 3) void p128_nodes(P128Args A) {
   __shared__ __attribute__((aligned(16))) uint32_t lk[4 * BLOCK];
+  const int64_t units = A.tstart[tiles_of(A.count)];
+  if (units == 0) return;  // (the whole workgroup)
   stage_keys(A.keys, lk);
   const int lane = (int)(threadIdx.x & 63u);
-  const int64_t units = A.start[A.count];
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
   for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw)
     node_unit(A, lk, g, lane);
 }
 
-// Strings of one block (at most 127 data words), four lanes per string:
-// lane j holds words j, j + 4, ..., four at a time, read at once through a
-// buffer resource over the wave's sixteen strings' bytes (range-checked per
-// dword: past the buffer's last dword the reads are zeros) and masked to
-// the padded string (Sec. 4); the four sums are added, folded and stored
-// (the root is level 1). A wave whose strings span 2 GiB or more (a long
-// string between them) reads word by word with guarded loads instead.
-constexpr int SG = 4;   // lanes per short string
+// Strings of one block (at most 127 data words) longer than the tiny ones,
+// four lanes per string: lane j holds words j, j + 4, ..., four at a time,
+// read at once through a buffer resource over the wave's strings' bytes
+// (range-checked per dword: past the buffer's last dword the reads are
+// zeros) and masked to the padded string (Sec. 4); the four sums are added,
+// folded and stored (the root is level 1). A wave whose strings span 2 GiB or
+// more (a long string between them) reads word by word with guarded loads
+// instead. Lanes with `mine` hold string s (lane j of its four).
+constexpr int SG = 4;   // lanes per string
 constexpr int SWL = 4;  // words per lane and round
-__global__ __launch_bounds__(256) void p128_short(P128Args A) {
-  __shared__ __attribute__((aligned(16))) uint32_t lk[4 * BLOCK];
-  stage_keys(A.keys, lk);
-  const int lane = (int)(threadIdx.x & 63u);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = t / SG;
-  const int j = (int)(t % SG);
-  const bool act = s < A.count;
-  const int64_t len = act ? str_len(A.off, s, A.buf_bytes) : 0;
-  const bool mine = act && blocks_of(len) == 1;
+__device__ void short4(const P128Args& A, const uint32_t* lk, bool mine, int64_t s, int j) {
+  const int64_t len = mine ? str_len(A.off, s, A.buf_bytes) : 0;
   const int64_t o0 = len ? A.off[s] : 0;
   const uint8_t* str = A.buf + o0;
   const uint32_t sh = (uint32_t)((uintptr_t)str & 3u);
@@ -538,6 +541,102 @@ __global__ __launch_bounds__(256) void p128_short(P128Args A) {
   }
 }
 
+// Tiny strings (at most TINY_BYTES, 17 words), one lane each, out of the
+// wave's LDS stage (stage_strings): every word but the last lies wholly
+// inside the string, the last one is masked to the padded string (Sec. 4);
+// one word's LDS reads are issued before the word ahead of it is summed.
+constexpr int64_t TINY_BYTES = 271;
+__device__ __forceinline__ void hash_staged128(const P128Args& A, const uint32_t* lk, const uint8_t* stage, int64_t i,
+                                               bool in, uint32_t p0, uint32_t sh, uint32_t ulen) {
+  wait_vm0();
+  const uint32_t nw = in ? ulen / W16 + 1 : 0u;  // words, the pad's included
+  const uint32_t maxw = wave_max(nw);
+  D7 acc;
+  zero(acc);
+  struct Wd {
+    uint32_t d[5];
+    uint4 k;
+  };
+  pipelined<2, Wd>(
+      maxw > 0 ? maxw - 1 : 0u,
+      [&](Wd& r, uint32_t w) {
+        const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * w);
+#pragma unroll
+        for (int u = 0; u < 5; ++u) r.d[u] = q[u];
+        r.k = *(const uint4*)(lk + 4 * w);  // a_{1,w} as four 32-bit limbs
+      },
+      [&](const Wd& r, uint32_t w) {
+        if (w + 1 >= nw) return;  // lanes past their full words sit out
+        uint32_t x[4];
+        word_dwords(r.d, sh, false, 0, x);
+        const uint32_t a[4] = {r.k.x, r.k.y, r.k.z, r.k.w};
+        mac128(acc, a, x);
+      });
+  if (!in) return;
+  const uint32_t wl = nw - 1;  // the word that holds the end
+  const uint32_t* q = (const uint32_t*)(stage + p0 + 16 * wl);
+  uint32_t d[5];
+#pragma unroll
+  for (int u = 0; u < 5; ++u) d[u] = q[u];
+  const uint4 kv = *(const uint4*)(lk + 4 * wl);
+  const uint32_t a[4] = {kv.x, kv.y, kv.z, kv.w};
+  uint32_t x[4];
+  word_dwords(d, sh, true, (int64_t)ulen - W16 * (int64_t)wl, x);
+  mac128(acc, a, x);
+  A5 sum = collapse(acc);
+  add_b(sum, A.keys, 1);
+  store128(A.out, A.flags, i, fold(sum));
+}
+
+// Strings of one block in tiles of 64 consecutive strings, persistent waves
+// (wave w takes tiles w, w + W, ...): tiny strings one lane each, the other
+// strings of one block four lanes each, sixteen at a time. Each tile's units
+// (parts of level-2 nodes of its longer strings) are counted for the node
+// kernels.
+__global__ __launch_bounds__(256, 2) void p128_tiles(P128Args A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lk[4 * BLOCK];
+  __shared__ __attribute__((aligned(16))) uint8_t stages[4][STAGE_BYTES + STAGE_SLACK];
+  __shared__ __attribute__((aligned(16))) uint32_t tables[4][STAGE_CHUNKS];
+  stage_keys(A.keys, lk);
+  const int lane = lane_id();
+  const int wv = (int)(threadIdx.x / 64);
+  uint8_t* stage = stages[wv];
+  uint32_t* table = tables[wv];
+  const int64_t nt = tiles_of(A.count);
+  const int64_t nwv = (int64_t)gridDim.x * 4;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wv; t < nt; t += nwv) {
+    const int64_t i = t * TILE + lane;
+    const bool act = i < A.count;
+    const int64_t len = act ? str_len(A.off, i, A.buf_bytes) : 0;
+    const int64_t o0 = len ? A.off[i] : 0;
+    uint64_t tot = 0;
+    (void)wave_excl_scan(act ? (uint32_t)units_of(len) : 0u, &tot);
+    if (lane == 0) A.tcnt[t] = (uint32_t)tot;
+    const bool tiny = act && len <= TINY_BYTES;
+    stage_strings(A.buf, tiny, o0, (uint32_t)len, stage, table, [&](bool in, uint32_t p0, uint32_t sh) {
+      hash_staged128(A, lk, stage, i, in, p0, sh, (uint32_t)len);
+    });
+    uint64_t rest = __ballot(act && !tiny && blocks_of(len) == 1);
+    while (rest) {
+      // the lanes of the next sixteen such strings, in lane order
+      const uint32_t rank =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(rest >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rest, 0u));
+      const bool pick = ((rest >> lane) & 1ull) && rank < 64 / SG;
+      wait_lgkm0();  // earlier readers of the table are done
+      if (pick) table[rank] = (uint32_t)lane;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint64_t picked = __ballot(pick);
+      const int g = lane / SG;
+      const bool have = g < __popcll(picked);
+      const int src = have ? (int)table[g] : lane;
+      short4(A, lk, have, t * TILE + src, lane % SG);
+      rest &= ~picked;
+    }
+  }
+}
+
 __device__ __forceinline__ void add_fe(A5& s, const F128& z) {
   add_at(s, (u128)z.lo | ((u128)z.hi << 64), 0);
   if (z.top) add_at(s, (u128)1, 2);
@@ -548,13 +647,13 @@ __device__ __forceinline__ void add_fe(A5& s, const F128& z) {
 // 3 and up. Each step writes its values over the previous ones: value q goes
 // to index q, at or below its first input; a wave's loads of a step are done
 // before its stores, and steps are ordered by a fence.
-__device__ void climb_string(const P128Args& A, int64_t s, int lane) {
+__device__ void climb_string(const P128Args& A, int64_t s, int64_t start, int lane) {
   const int64_t len = str_len(A.off, s, A.buf_bytes);
   const int64_t n1 = blocks_of(len);
   if (n1 == 1) return;
   const int64_t nq = (n1 + QB - 1) / QB;  // unit values
-  if ((uint64_t)(A.start[s] + nq) > A.zcap) return;
-  F128* v = A.z2 + A.start[s];
+  if ((uint64_t)(start + nq) > A.zcap) return;
+  F128* v = A.z2 + start;
   int64_t n = (n1 + BLOCK - 1) / BLOCK;  // level-2 values
   for (int64_t k0 = 0; k0 < n; k0 += 64) {
     const int64_t k = k0 + lane;
@@ -596,11 +695,11 @@ __device__ void climb_string(const P128Args& A, int64_t s, int lane) {
 // Persistent waves over the units; a string's first unit climbs it.
 __global__ __launch_bounds__(256) void p128_upper(P128Args A) {
   const int lane = (int)(threadIdx.x & 63u);
-  const int64_t units = A.start[A.count];
+  const int64_t units = A.tstart[tiles_of(A.count)];
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
   for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; g < units; g += nw) {
-    const int64_t s = unit_string(A, g, lane);
-    if (g == A.start[s]) climb_string(A, s, lane);
+    const UnitPos up = unit_at(A, g, lane);
+    if (up.k == 0) climb_string(A, up.s, up.start, lane);
   }
 }
 
@@ -611,34 +710,46 @@ unsigned grid_for(int64_t threads) {
 
 }  // namespace
 
-// scratch: counts (4 per string, rounded to 8), unit starts (8 per string
-// and one), the scan's tile totals, then 32 bytes per possible unit
+// scratch: unit counts (4 per tile of 64 strings, rounded to 8), tile starts
+// (8 per tile and one), the scan's tile totals, then 32 bytes per possible
+// unit
 uint64_t pm128_scratch_bytes(int64_t count, uint64_t buf_bytes) {
   const uint64_t n = (uint64_t)count;
+  const uint64_t nt = (n + TILE - 1) / TILE;
   const uint64_t units = 2 * n + buf_bytes / (BLK_BYTES * QB) + 2;
-  return ((4 * n + 7) & ~7ull) + 8 * (n + 1) + excl_scan_work_bytes(n) + sizeof(F128) * units;
+  return ((4 * nt + 7) & ~7ull) + 8 * (nt + 1) + excl_scan_work_bytes(nt) + sizeof(F128) * units;
 }
 
 hipError_t launch_pm128(const uint8_t* buf, uint64_t buf_bytes, const int64_t* offsets, int64_t count,
                         const uint64_t* keys, void* out, uint32_t flags, void* scratch, hipStream_t st) {
   const uint64_t n = (uint64_t)count;
+  const uint64_t nt = (n + TILE - 1) / TILE;
   char* p = (char*)scratch;
-  uint32_t* cnt = (uint32_t*)p;
-  p += (4 * n + 7) & ~7ull;
-  int64_t* start = (int64_t*)p;
-  p += 8 * (n + 1);
+  uint32_t* tcnt = (uint32_t*)p;
+  p += (4 * nt + 7) & ~7ull;
+  int64_t* tstart = (int64_t*)p;
+  p += 8 * (nt + 1);
   uint64_t* bsum = (uint64_t*)p;
-  p += excl_scan_work_bytes(n);
+  p += excl_scan_work_bytes(nt);
   F128* z2 = (F128*)p;
   const uint64_t units_bound = 2 * n + buf_bytes / (BLK_BYTES * QB) + 2;
-  hipLaunchKernelGGL(p128_count, dim3(grid_for(count) > 65536 ? 65536 : grid_for(count)), dim3(256), 0, st, offsets,
-                     count, buf_bytes, cnt);
-  hipError_t e = launch_excl_scan_u32(cnt, n, start, bsum, st);
+  P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, tcnt, tstart, z2, units_bound};
+  // the tile kernel: persistent, two workgroups of four waves per CU
+  static std::atomic<int> cus_of[64];  // CUs per device, looked up once
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  int cus = cus_of[dev].load(std::memory_order_relaxed);
+  if (!cus) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      return hipErrorInvalidDevice;
+    cus_of[dev].store(cus, std::memory_order_relaxed);
+  }
+  const uint64_t tgrid = (nt + 3) / 4 < 2 * (uint64_t)cus ? (nt + 3) / 4 : 2 * (uint64_t)cus;
+  if (nt) hipLaunchKernelGGL(p128_tiles, dim3((unsigned)tgrid), dim3(256), 0, st, a);
+  hipError_t e = launch_excl_scan_u32(tcnt, nt, tstart, bsum, st);
   if (e != hipSuccess) return e;
-  P128Args a{buf, buf_bytes, offsets, count, keys, out, flags, start, z2, units_bound};
   // persistent grids: at most 8192 waves, fewer when the units are fewer
   const int64_t waves = units_bound < 8192 ? (int64_t)units_bound : 8192;
-  hipLaunchKernelGGL(p128_short, dim3(grid_for(count * SG)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_nodes, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(p128_upper, dim3(grid_for(waves * 64)), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -1,7 +1,7 @@
 """PM+128 (p = 2^128 + 51) on the GPU against the oracle (oracle/pm128.py,
 exact Python integers), bit for bit: edge lengths at every alignment, the
-level transitions up to four levels, flags, a C2-shaped batch and offsets out
-of order. Expected values come from the oracle only."""
+level transitions up to four levels, flags, a C2-shaped batch, tiles mixing
+every length class and offsets out of order. Expected values come from the oracle only."""
 from __future__ import annotations
 
 import numpy as np
@@ -81,6 +81,22 @@ def test_pm128_c2_shaped():
     rng = np.random.default_rng(920)
     rg = W.from_lengths(rng.integers(8, 257, 3000), 921, True)
     check(rg.buf, rg.offsets, 3, 0, "c2-shaped 3000")
+
+
+@pytest.mark.parametrize("lead", [0, 1])
+def test_pm128_tiles_mixed(lead):
+    """Tiles of 64 strings mixing the one-lane lengths (up to 271 bytes), the
+    longer strings of one block and strings of several blocks, with the
+    boundary lengths 271 / 272 and 2031 / 2032; 700 strings (the last tile
+    partial). A long string between short ones makes a tile's short strings
+    span more than the stage, so both staging forms run."""
+    rng = np.random.default_rng(950 + lead)
+    kinds = rng.integers(0, 10, 700)
+    lengths = np.where(kinds < 6, rng.integers(0, 272, 700),
+                       np.where(kinds < 9, rng.integers(272, 2032, 700), rng.integers(2032, 40000, 700)))
+    lengths[:8] = [271, 272, 270, 273, 2031, 2032, 0, 271]
+    rg = W.from_lengths(lengths, 951 + lead, True, lead=lead)
+    check(rg.buf, rg.offsets, 4, 0, f"mixed tiles lead={lead}")
 
 
 def test_pm128_four_levels():
