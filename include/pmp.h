@@ -111,11 +111,14 @@ int pmp_plan_status(pmp_plan* plan, pmp_stream_t stream);
 int pmp_plan_set_tile(pmp_plan* plan, int wide, int lanes_per_block);
 /* Launch shape: waves per CU (0 = as many as stay resident), the per-string
  * work weight alpha in byte equivalents used to split a batch between waves
- * (0 = keep; a new plan has 768), the smallest share of work worth a wave
+ * (0 = keep; a new plan has 768; PMP_ALPHA_BY_COUNT splits by string count
+ * alone, which needs no search of the offsets and suits batches of strings
+ * of similar lengths), the smallest share of work worth a wave
  * (0 = keep; a new plan has 8192), and the
  * number of shares each wave takes, spread over the batch (1..64, 0 = keep;
  * more shares even out regions of the batch that cost more per byte, at a
  * small search cost per share). */
+#define PMP_ALPHA_BY_COUNT 0xFFFFFFFFu
 int pmp_plan_tune(pmp_plan* plan, int waves_per_cu, uint32_t alpha, uint64_t wave_bytes, int shares_per_wave);
 
 /* ---------------------------------------------------------------------- */
@@ -215,7 +218,7 @@ int pmp_graph_destroy(pmp_graph* graph);
 
 /* Autotuner: times pmp_hash_many(plan, batches, nbatch, stream) over every
  * compiled lanes-per-block pair and per-string weight alpha in {256, 512, 768, 1024,
- * 1536, 2048},
+ * 1536, 2048, PMP_ALPHA_BY_COUNT},
  * then over 1, 2 and 4 shares per wave, then over launch widths of 4, 12 and
  * 16 waves per CU, each stage on the best of the one before; leaves the
  * fastest setting in the plan and reports it in *best (may be NULL). The

@@ -245,7 +245,8 @@ int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, Prepared&
     B.slots = plan->slots + base;
     B.nslots = slots_for(list[k]->buf_bytes, (int)list[k]->wide);
     B.work0 = work;
-    B.work = (uint64_t)plan->alpha * (uint64_t)list[k]->count + list[k]->buf_bytes;
+    B.work = plan->alpha == PMP_ALPHA_BY_COUNT ? (uint64_t)list[k]->count
+                                               : (uint64_t)plan->alpha * (uint64_t)list[k]->count + list[k]->buf_bytes;
     work += B.work;
     base += B.nslots;
   }
@@ -260,13 +261,16 @@ int prepare(pmp_plan* plan, const std::vector<const pmp_batch*>& list, Prepared&
   if (per_cu <= 0) per_cu = 4 * batch_blocks_per_cu(plan->g32, plan->g64);
   if (per_cu <= 0) per_cu = 8;
   const uint64_t max_waves = (uint64_t)plan->cus * (uint64_t)per_cu;
-  uint64_t waves = (work + plan->wave_bytes - 1) / plan->wave_bytes;
+  // (split by count: one wave per 64 strings at most)
+  const bool by_count = plan->alpha == PMP_ALPHA_BY_COUNT;
+  const uint64_t unit = by_count ? 64 : plan->wave_bytes;
+  uint64_t waves = (work + unit - 1) / unit;
   if (waves < 1) waves = 1;
   if (waves > max_waves) waves = max_waves;
   P.a.total_waves = (uint32_t)waves;
   // small launches keep one share per wave
   uint64_t per_wave = (uint64_t)plan->shares_per_wave;
-  while (per_wave > 1 && work / (waves * per_wave) < plan->wave_bytes / 2) per_wave /= 2;
+  while (per_wave > 1 && work / (waves * per_wave) < unit / 2) per_wave /= 2;
   P.a.per_wave = (uint32_t)per_wave;
   P.a.total = work;
   P.a.share = (work + waves * per_wave - 1) / (waves * per_wave);
@@ -670,7 +674,7 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
   };
   int pairs[16][2];
   const int np = pmp::batch_tile_pairs(pairs, 16);
-  const uint32_t alphas[] = {256, 512, 768, 1024, 1536, 2048};
+  const uint32_t alphas[] = {256, 512, 768, 1024, 1536, 2048, PMP_ALPHA_BY_COUNT};
   int r = PMP_OK;
   for (int t = 0; t < np && !r; ++t)
     for (uint32_t al : alphas)

@@ -35,19 +35,21 @@ struct BatchArgs {
   Slot* slots;  // ceil(buf_bytes / (128 W)) + 2 node accumulators
   uint64_t nslots;
   uint64_t work0;  // work of the batches before this one
-  uint64_t work;   // alpha * count + buf_bytes
+  uint64_t work;   // alpha * count + buf_bytes (count when split by count)
 };
 
 // The work of a launch is the sum over batches of alpha * count + buf_bytes:
 // string i of a batch starts at work position work0 + alpha * i + offsets[i]
-// (a byte of buffer and a string each count as work). The work is cut into
+// (a byte of buffer and a string each count as work). With alpha =
+// PMP_ALPHA_BY_COUNT a string is one unit of work whatever its length, and
+// string i starts at work0 + i. The work is cut into
 // per_wave * total_waves shares of `share` units; wave w takes shares w,
 // w + total_waves, w + 2 total_waves, ...
 struct KArgs {
   BatchArgs b[2];              // up to two batches travel in the arguments...
   const BatchArgs* batches;    // ...more come as a device array (else null)
   uint32_t nbatch;
-  uint32_t alpha;        // per-string work in byte equivalents
+  uint32_t alpha;        // per-string work in byte equivalents (PMP_ALPHA_BY_COUNT: strings only)
   int32_t* status;       // device status word (STATUS_* bits)
   uint32_t total_waves;  // waves sharing the work
   uint32_t per_wave;     // shares per wave

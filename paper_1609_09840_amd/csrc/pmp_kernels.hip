@@ -981,8 +981,14 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(KArgs A) {
           }
         }
         Pos ps, pe;
-        if (B.wide) locate2<8>(B, A.alpha, lo, hi, ps, pe);
-        else locate2<4>(B, A.alpha, lo, hi, ps, pe);
+        if (A.alpha == PMP_ALPHA_BY_COUNT) {  // the work of a string is 1: [lo, hi) are its strings
+          ps = Pos{(int64_t)lo, 0};
+          pe = Pos{(int64_t)hi, 0};
+        } else if (B.wide) {
+          locate2<8>(B, A.alpha, lo, hi, ps, pe);
+        } else {
+          locate2<4>(B, A.alpha, lo, hi, ps, pe);
+        }
         if (restage) {
           __builtin_amdgcn_wave_barrier();  // all lanes done with the previous keys
 #pragma unroll

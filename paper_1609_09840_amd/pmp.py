@@ -23,6 +23,7 @@ PMP_E_HIP = -5
 PMP_E_NOMEM = -6
 PMP_NOALLOC_SCRATCH_BYTES = 16 << 20  # include/pmp.h
 PMP_E_INTERNAL = -7
+PMP_ALPHA_BY_COUNT = 0xFFFFFFFF  # pmp_plan_tune: split batches by string count
 
 PMP_NO_MIX = 1
 PMP_OUT_FIELD = 2

@@ -257,6 +257,48 @@ def test_tiles_agree():
             plan.close()
 
 
+@pytest.mark.parametrize("shares", [1, 4])
+def test_split_by_count(shares):
+    """Shares cut by string count (PMP_ALPHA_BY_COUNT, no offset search):
+    every string whole in one wave's share, long ones with several level-2
+    nodes included; one batch per variant, then five batches in one launch."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    rng = np.random.default_rng(97 + shares)
+    specs = []
+    for k, wide in enumerate((False, True, False, True, False)):
+        lengths = np.concatenate([rng.integers(0, 272, 500), rng.integers(272, 40000, 60), [0, 300000, 1, 200000]])
+        rng.shuffle(lengths)
+        specs.append(W.from_lengths(lengths[: 300 + 100 * k], 98 + k, wide, lead=k))
+    plan = pmp.Plan(0)
+    plan.tune(0, pmp.PMP_ALPHA_BY_COUNT, 0, shares)
+    for rg in specs[:2]:
+        keys = U.keys_for(rg.wide, 99)
+        say(f"case by-count shares={shares} wide={rg.wide} count={rg.count}")
+        got = U.gpu_hash(rg, keys, 2, plan=plan)
+        want = U.oracle_hash(rg, keys, 2)
+        assert U.first_mismatch(got, want) is None, U.first_mismatch(got, want)
+    say(f"case by-count shares={shares} five batches")
+    k32, k64 = U.keys_for(False, 99), U.keys_for(True, 99)
+    d32, d64 = U.to_dev_keys(k32), U.to_dev_keys(k64)
+    keep, batches = [], []
+    for rg in specs:
+        buf, off = U.to_dev(rg)
+        out = torch.zeros(rg.count, dtype=torch.uint64 if rg.wide else torch.uint32, device=U.dev())
+        keep.append((rg, out, buf, off))
+        batches.append(pmp.make_batch(rg.wide, buf, off, d64 if rg.wide else d32, out, 0))
+    pmp.pmp_hash_many(batches, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == pmp.PMP_OK
+    for rg, out, _, _ in keep:
+        got = U.as_u64(out.cpu().numpy())
+        want = U.oracle_hash(rg, k64 if rg.wide else k32, 0)
+        assert U.first_mismatch(got, want) is None, U.first_mismatch(got, want)
+    plan.close()
+
+
 def test_plain_form_matches():
     """The one-string-per-launch baseline gives identical results."""
     import torch
