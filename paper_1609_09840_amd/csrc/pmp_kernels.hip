@@ -828,16 +828,12 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
 
 // All blocks in [ps, pe) of one batch, 64 strings at a time.
 template <bool WIDE, int G>
-__device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk, uint8_t* stage, uint32_t* table,
-                          Pos ps, Pos pe) {
+__device__ void run_range(const KArgs& A, const BatchArgs& B, uint64_t* lk, uint8_t* stage, uint32_t* table,
+                          Pos ps, Pos pe, bool restage, const uint64_t (&kv)[4]) {
   using T = Tr<WIDE>;
   constexpr int W = T::W;
   constexpr int WPG = 16 / W;
   const int lane = lane_id();
-  if (pe.i < ps.i || (pe.i == ps.i && pe.c < ps.c)) {  // only possible when offsets decrease somewhere
-    if (lane == 0) __hip_atomic_fetch_or(A.status, STATUS_OFFSETS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
-  }
   const int64_t last = pe.c > 0 ? pe.i : pe.i - 1;  // last string with blocks here
   // each tile's offsets are loaded while the tile before it is hashed
   int64_t n0 = 0, n1 = 0;
@@ -851,6 +847,21 @@ __device__ void run_range(const KArgs& A, const BatchArgs& B, const uint64_t* lk
     }
   };
   tile_offsets(ps.i);
+  // the batch's keys (loaded by the caller) go to LDS once the first tile's
+  // offsets are on their way
+  if (restage) {
+    __builtin_amdgcn_wave_barrier();  // all lanes done with the previous keys
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lk[lane + 64 * q] = kv[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // (the keys are staged even for an empty range: the caller counts on them)
+  if (pe.i < ps.i || (pe.i == ps.i && pe.c < ps.c)) {  // only possible when offsets decrease somewhere
+    if (lane == 0) __hip_atomic_fetch_or(A.status, STATUS_OFFSETS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   for (int64_t t0 = ps.i; t0 <= last; t0 += 64) {
     const int64_t i = t0 + lane;
     const bool in = i <= last && i < B.count;
@@ -989,18 +1000,12 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(KArgs A) {
         } else {
           locate2<4>(B, A.alpha, lo, hi, ps, pe);
         }
+        if (B.wide) run_range<true, G64>(A, B, lk, stage, table, ps, pe, restage, kv);
+        else run_range<false, G32>(A, B, lk, stage, table, ps, pe, restage, kv);
         if (restage) {
-          __builtin_amdgcn_wave_barrier();  // all lanes done with the previous keys
-#pragma unroll
-          for (int q = 0; q < 4; ++q) lk[lane + 64 * q] = kv[q];
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           staged = B.keys;
           staged_wide = B.wide;
         }
-        if (B.wide) run_range<true, G64>(A, B, lk, stage, table, ps, pe);
-        else run_range<false, G32>(A, B, lk, stage, table, ps, pe);
       }
       if (past) break;
     }
