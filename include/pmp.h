@@ -220,8 +220,10 @@ int pmp_graph_destroy(pmp_graph* graph);
  * compiled lanes-per-block pair and per-string weight alpha in {256, 512, 768, 1024,
  * 1536, 2048, PMP_ALPHA_BY_COUNT},
  * then over 1, 2 and 4 shares per wave, then over launch widths of 4, 12 and
- * 16 waves per CU, each stage on the best of the one before; leaves the
- * fastest setting in the plan and reports it in *best (may be NULL). The
+ * 16 waves per CU, each stage on the best of the one before (three launches
+ * a setting), then times the four fastest again over ten launches each;
+ * leaves the fastest setting in the plan and reports it in *best (may be
+ * NULL). The
  * outputs are written by every timed launch (same values). The stream is
  * synchronized. */
 typedef struct pmp_tuning {

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "pmp.h"
@@ -637,10 +638,9 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   // time one configuration: one warm launch, then the mean of `reps`
-  auto measure = [&](float* ms) -> int {
+  auto measure = [&](float* ms, int reps) -> int {
     int r = pmp_hash_many(plan, batches, nbatch, stream);
     if (r) return r;
-    const int reps = 3;
     hipError_t x = hipEventRecord(e0, s);
     for (int k = 0; k < reps && !r; ++k) r = pmp_hash_many(plan, batches, nbatch, stream);
     if (r) return r;
@@ -662,13 +662,15 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
     plan->waves_per_cu = t.waves_per_cu;
     plan->shares_per_wave = t.shares_per_wave;
   };
+  std::vector<pmp_tuning> seen;  // every setting tried, with its time
   auto trial = [&](pmp_tuning t) -> int {
     apply(t);
     float ms = 0;
-    const int rr = measure(&ms);
-    if (!rr && ms < top.ms) {
+    const int rr = measure(&ms, 3);
+    if (!rr) {
       t.ms = ms;
-      top = t;
+      seen.push_back(t);
+      if (ms < top.ms) top = t;
     }
     return rr;
   };
@@ -685,6 +687,22 @@ int pmp_plan_autotune(pmp_plan* plan, const pmp_batch* batches, int32_t nbatch, 
   const int wpcs[] = {4, 12, 16};
   for (int wv : wpcs)
     if (!r) r = trial(pmp_tuning{top.g32, top.g64, top.alpha, wv, top.shares_per_wave, 0.f});
+  // the four fastest settings timed again over ten launches each: short
+  // timings of settings within a few percent of each other are noisy
+  if (!r && seen.size() > 1) {
+    std::sort(seen.begin(), seen.end(), [](const pmp_tuning& a, const pmp_tuning& b) { return a.ms < b.ms; });
+    top.ms = 1e30f;
+    for (size_t k = 0; k < seen.size() && k < 4 && !r; ++k) {
+      pmp_tuning t = seen[k];
+      apply(t);
+      float ms = 0;
+      r = measure(&ms, 10);
+      if (!r && ms < top.ms) {
+        t.ms = ms;
+        top = t;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const pmp_tuning keep = r ? cur : top;
