@@ -375,8 +375,10 @@ int pmp_hash128(const uint8_t* d_buf, uint64_t buf_bytes, const int64_t* d_offse
  * d_result[q] = the smallest key index i whose bytes equal query q's, or -1.
  * `keys` is the batch given to the build (its buf is read; the entries hold
  * the rest); queries and keys must share wide, the key table pointer and the
- * flags. Returns PMP_E_INVALID_ARG on NULL pointers, mismatched batches or M
- * out of range. */
+ * flags. The byte comparison loads whole 16-byte-aligned granules that hold
+ * a byte of the query or key compared (as the short-string path of the hash
+ * does), never other memory. Returns PMP_E_INVALID_ARG on NULL pointers,
+ * mismatched batches or M out of range. */
 typedef struct pmp_table_entry {
   int64_t key;     /* key index in the build's batch */
   uint64_t hash;   /* its n-bit output (PM+32: zero-extended) */

@@ -13,9 +13,9 @@
 //
 // Probe (after the queries are hashed): one lane per query walks its bucket
 // for the smallest key with the query's full n-bit hash and length, then
-// compares that key's bytes once (all lanes of a wave together, after the
-// walk); only when a full-hash collision has different bytes does the lane
-// compare every such key. The result is the smallest equal key index, or -1.
+// compares that key's bytes, 64 at a time from 16-byte loads; only when a
+// full-hash collision has different bytes does the lane go on to the next
+// such key. The result is the smallest equal key index, or -1.
 #include "pmp_device.hpp"
 #include "pmp_internal.h"
 
@@ -126,51 +126,71 @@ __device__ __forceinline__ const uint32_t* gdw(uint64_t a) {
   return (const uint32_t*)(const __attribute__((address_space(1))) uint32_t*)(uintptr_t)a;
 }
 
-// Bytes [o, o + take) of a string at p (take <= 16) as four little-endian
-// dwords, zero past `take`: the aligned dwords holding them are loaded (each
-// holds at least one wanted byte) and realigned.
-__device__ __forceinline__ void load16_of(const uint8_t* p, int64_t o, uint32_t take, uint32_t* x) {
+// Records read per round of the bucket walk, and bytes compared per round:
+// a wave waits for its slowest lane, so each round issues all of its loads
+// before it uses any. At load factor 1 a bucket rarely holds more than a few
+// keys; wider compare steps cost registers (occupancy) for fewer rounds.
+constexpr int RECS = 2;
+constexpr int STEP = 64;
+
+// Bytes [o, o + STEP) of a string at p as STEP / 4 little-endian dwords
+// (r = bytes of the string left from o, r > 0; dwords past its end hold
+// anything). The 16-byte chunks of the aligned region around those bytes are
+// loaded, every chunk that holds a byte of the string from its own address
+// (such a chunk lies in the string's memory page) and any other one from the
+// first chunk's, so that no load is conditional; then the chunks are shifted
+// down by the string's offset in its first chunk: whole dwords with two
+// rounds of selects, then bytes with alignbyte.
+__device__ __forceinline__ void load_step(const uint8_t* p, int64_t o, int64_t r, uint32_t* x) {
+  constexpr int NC = STEP / 16 + 1;  // chunks that can hold the bytes
   const uint64_t a = (uint64_t)(uintptr_t)p + (uint64_t)o;
-  const uint32_t sh = (uint32_t)(a & 3u);
-  const uint32_t* w = gdw(a - sh);
-  uint32_t d[5];
+  const uint32_t lead = (uint32_t)(a & 15u);
+  const uint64_t base = a - lead;
+  const uint32_t lim = lead + (uint32_t)(r < STEP ? r : STEP);  // chunk c holds a wanted byte iff 16c < lim
+  uint32_t d[4 * NC];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) d[k] = 4u * k < sh + take ? w[k] : 0u;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    uint32_t v = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
-    const int32_t left = (int32_t)take - 4 * k;  // wanted bytes in this dword
-    if (left <= 0) v = 0;
-    else if (left < 4) v &= (1u << (8 * left)) - 1u;
-    x[k] = v;
+  for (int c = 0; c < NC; ++c) {
+    const uint4 q = *(const uint4*)gdw(16u * c < lim ? base + 16u * c : base);
+    d[4 * c] = q.x;
+    d[4 * c + 1] = q.y;
+    d[4 * c + 2] = q.z;
+    d[4 * c + 3] = q.w;
   }
+  // v_perm_b32 picks bytes 4..7 (its first operand) or 0..3 (its second):
+  // written as selects, the shifts would become an indexed copy in scratch
+  const uint32_t s2 = (lead & 8u) ? 0x07060504u : 0x03020100u;
+  const uint32_t s1 = (lead & 4u) ? 0x07060504u : 0x03020100u;
+#pragma unroll
+  for (int k = 0; k + 2 < 4 * NC; ++k) d[k] = __builtin_amdgcn_perm(d[k + 2], d[k], s2);
+#pragma unroll
+  for (int k = 0; k + 1 < 4 * NC; ++k) d[k] = __builtin_amdgcn_perm(d[k + 1], d[k], s1);
+#pragma unroll
+  for (int k = 0; k < STEP / 4; ++k) x[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], lead & 3u);
 }
 
-// 32 bytes per step, both strings' loads issued before the comparison
-__device__ bool bytes_equal(const uint8_t* a, const uint8_t* b, int64_t len) {
-  for (int64_t o = 0; o < len; o += 32) {
+// STEP bytes per round, both strings' loads issued before the comparison;
+// the differences are masked to the bytes of the strings
+__device__ __forceinline__ bool bytes_equal(const uint8_t* a, const uint8_t* b, int64_t len) {
+  for (int64_t o = 0; o < len; o += STEP) {
     const int64_t r = len - o;
-    const uint32_t t0 = r < 16 ? (uint32_t)r : 16u;
-    const uint32_t t1 = r <= 16 ? 0u : (r < 32 ? (uint32_t)(r - 16) : 16u);
-    uint32_t xa[8], xb[8];
-    load16_of(a, o, t0, xa);
-    load16_of(b, o, t0, xb);
-    if (t1) {
-      load16_of(a, o + 16, t1, xa + 4);
-      load16_of(b, o + 16, t1, xb + 4);
-    } else {
-#pragma unroll
-      for (int k = 4; k < 8; ++k) xa[k] = xb[k] = 0;
-    }
+    uint32_t xa[STEP / 4], xb[STEP / 4];
+    load_step(a, o, r, xa);
+    load_step(b, o, r, xb);
+    const uint32_t rr = (uint32_t)(r < STEP ? r : STEP);
     uint32_t diff = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) diff |= xa[k] ^ xb[k];
+    for (int k = 0; k < STEP / 4; ++k) {
+      const uint32_t v = xa[k] ^ xb[k];
+      // bytes 4k .. 4k + 3 of the step that lie inside the string
+      const uint32_t keep = 4u * k + 4 <= rr ? ~0u : (4u * k < rr ? (1u << (8 * (rr - 4u * k))) - 1u : 0u);
+      diff |= v & keep;
+    }
     if (diff) return false;
   }
   return true;
 }
 
-__global__ void tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
+__global__ void __launch_bounds__(256) tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
                           uint32_t wide, uint64_t m, const int64_t* start, const pmp_table_entry* entries,
                           int64_t* result) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
@@ -178,25 +198,31 @@ __global__ void tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, 
     const uint64_t hq = hash_at(qh, wide, q);
     const uint64_t b = hq % m;
     const int64_t e0 = start[b], e1 = start[b + 1];
-    // the smallest key with the query's hash and length; the answer if its
-    // bytes are equal (every equal key has that hash and length)
-    int64_t cand = -1, coff = 0;
-    for (int64_t e = e0; e < e1; ++e) {
-      const pmp_table_entry r = entries[e];
-      if (r.hash == hq && r.length == len && (cand < 0 || r.key < cand)) {
-        cand = r.key;
-        coff = r.offset;
+    // Candidates in increasing key order: the smallest key above `lo` with
+    // the query's hash and length (every equal key has both), then its bytes.
+    // The first candidate is nearly always the answer or there is none; a
+    // full-hash collision with different bytes sends the lane round again.
+    int64_t best = -1, lo = -1;
+    for (;;) {
+      int64_t cand = -1, coff = 0;
+      for (int64_t e = e0; e < e1; e += RECS) {
+        // records past the bucket's end are read from its first one, unused
+        pmp_table_entry r[RECS];
+#pragma unroll
+        for (int u = 0; u < RECS; ++u) r[u] = entries[e + u < e1 ? e + u : e];
+#pragma unroll
+        for (int u = 0; u < RECS; ++u)
+          if (e + u < e1 && r[u].hash == hq && r[u].length == len && r[u].key > lo && (cand < 0 || r[u].key < cand)) {
+            cand = r[u].key;
+            coff = r[u].offset;
+          }
       }
-    }
-    int64_t best = cand;
-    if (cand >= 0 && !bytes_equal(qbuf + q0, kbuf + coff, len)) {
-      // a full-hash collision with different bytes: compare every candidate
-      best = -1;
-      for (int64_t e = e0; e < e1; ++e) {
-        const pmp_table_entry r = entries[e];
-        if (r.hash != hq || r.length != len || r.key == cand || (best >= 0 && r.key > best)) continue;
-        if (bytes_equal(qbuf + q0, kbuf + r.offset, len)) best = r.key;
+      if (cand < 0) break;
+      if (bytes_equal(qbuf + q0, kbuf + coff, len)) {
+        best = cand;
+        break;
       }
+      lo = cand;
     }
     result[q] = best;
   }

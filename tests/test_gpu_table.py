@@ -219,3 +219,51 @@ def test_table_all_hashes_equal(wide):
     got = res.cpu().numpy()
     assert np.array_equal(got, want)
     assert (got >= 0).sum() >= 140
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_table_all_hashes_equal_long(wide):
+    """As above with keys of 1 to 300 bytes (one block each), so that equal
+    hash and length leave the bytes to decide: the queries copy keys whole
+    or with one byte changed at the first, last or a step boundary position
+    (bytes 0, 15, 16, 127, 128, 255 and the last), and lie at every offset
+    mod 16 from the keys."""
+    import torch
+
+    from paper_1609_09840_amd import pmp
+
+    say(f"case table all hashes equal, long keys: wide={wide}")
+    keys_np = U.keys_for(wide, 3 + wide).copy()
+    keys_np[:8 * 128] = 0
+    rng = np.random.default_rng(870)
+    kparts = key_set(600, 871, lo=1, hi=301, dup_every=7)
+    qparts = []
+    for q in range(900):
+        src = kparts[int(rng.integers(0, len(kparts)))].copy()
+        if q % 3 == 1:
+            cands = [p for p in (0, 15, 16, 127, 128, 255, src.size - 1) if p < src.size]
+            p = cands[int(rng.integers(0, len(cands)))]
+            src[p] ^= np.uint8(1 + rng.integers(0, 255))
+        elif q % 3 == 2:
+            src = rng.integers(0, 256, src.size).astype(np.uint8)
+        # a filler of 0..15 bytes moves the next query's offset mod 16
+        qparts.append(src)
+        qparts.append(rng.integers(0, 256, int(rng.integers(0, 16))).astype(np.uint8))
+    kbuf, koff = ragged(kparts)
+    qbuf, qoff = ragged(qparts)
+    keys = U.to_dev_keys(keys_np)
+    dk, dko = U.to_dev(W.Ragged(kbuf, koff, wide))
+    dq, dqo = U.to_dev(W.Ragged(qbuf, qoff, wide))
+    m = 64
+    t = pmp.pmp_table_build(wide, dk, dko, keys, m)
+    res = t.probe(dq, dqo)
+    torch.cuda.synchronize()
+    kh = oracle_hashes(wide, kbuf, koff, keys_np, 0)
+    qh = oracle_hashes(wide, qbuf, qoff, keys_np, 0)
+    assert len(set(kh.tolist())) == 1
+    want_start, want_entries = T.build(kh, m)
+    want = T.probe(kbuf, koff, kh, want_start, want_entries, qbuf, qoff, qh, m)
+    got = res.cpu().numpy()
+    assert np.array_equal(got, want)
+    assert (got[0::6] >= 0).all()  # the whole copies
+    assert (got[2::6] < 0).sum() >= 100  # most one-byte changes find no key
