@@ -96,12 +96,16 @@ __global__ void tab_scan_totals(uint64_t* bsum, uint64_t nb, int64_t* start, uin
   if (threadIdx.x == 0) start[m] = (int64_t)carry;
 }
 
-// Phase 3: add each tile's offset.
-__global__ void tab_scan_add(int64_t* start, uint64_t m, const uint64_t* bsum) {
+// Phase 3: add each tile's offset; with `clear`, the counts are set back to
+// zero on the way (the scatter's cursors), which saves a launch.
+__global__ void tab_scan_add(int64_t* start, uint64_t m, const uint64_t* bsum, uint32_t* clear) {
   const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
   const int64_t add = (int64_t)bsum[blockIdx.x];
   for (int k = threadIdx.x; k < SCAN_TILE; k += 256)
-    if (base + k < m) start[base + k] += add;
+    if (base + k < m) {
+      start[base + k] += add;
+      if (clear) clear[base + k] = 0;
+    }
 }
 
 // Each key's record (index, hash, offset, length) goes to its bucket: a
@@ -242,12 +246,20 @@ uint64_t table_work_bytes(uint64_t m) {
 
 uint64_t excl_scan_work_bytes(uint64_t m) { return 8 * ((m + SCAN_TILE - 1) / SCAN_TILE + 1); }
 
-hipError_t launch_excl_scan_u32(const uint32_t* cnt, uint64_t m, int64_t* start, uint64_t* bsum, hipStream_t s) {
+// Exclusive scan of m counts into start[0..m] (start[m] = the total); with
+// `clear`, the counts (at `clear`, the same array as cnt) are zeroed after
+// they are read.
+static hipError_t excl_scan(const uint32_t* cnt, uint64_t m, int64_t* start, uint64_t* bsum, uint32_t* clear,
+                            hipStream_t s) {
   const uint64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
   if (nb) hipLaunchKernelGGL(tab_scan_tiles, dim3((unsigned)nb), dim3(256), 0, s, cnt, m, start, bsum);
   hipLaunchKernelGGL(tab_scan_totals, dim3(1), dim3(256), 0, s, bsum, nb, start, m);
-  if (nb) hipLaunchKernelGGL(tab_scan_add, dim3((unsigned)nb), dim3(256), 0, s, start, m, bsum);
+  if (nb) hipLaunchKernelGGL(tab_scan_add, dim3((unsigned)nb), dim3(256), 0, s, start, m, bsum, clear);
   return hipGetLastError();
+}
+
+hipError_t launch_excl_scan_u32(const uint32_t* cnt, uint64_t m, int64_t* start, uint64_t* bsum, hipStream_t s) {
+  return excl_scan(cnt, m, start, bsum, nullptr, s);
 }
 
 hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t m, const int64_t* koff,
@@ -256,12 +268,11 @@ hipError_t launch_table_build(const void* h, uint32_t wide, int64_t n, uint64_t 
   uint64_t* bsum = (uint64_t*)((char*)work + ((4 * m + 7) & ~7ull));
   hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
   if (n > 0) hipLaunchKernelGGL(tab_count, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, cnt);
-  hipError_t e = launch_excl_scan_u32(cnt, m, start, bsum, s);
+  // the scan zeroes the counts for the scatter's cursors
+  hipError_t e = excl_scan(cnt, m, start, bsum, n > 0 ? cnt : nullptr, s);
   if (e != hipSuccess) return e;
-  if (n > 0) {
-    hipLaunchKernelGGL(tab_zero, dim3(grid_for((int64_t)m)), dim3(256), 0, s, cnt, m);
+  if (n > 0)
     hipLaunchKernelGGL(tab_scatter, dim3(grid_for(n)), dim3(256), 0, s, h, wide, n, m, koff, start, cnt, entries);
-  }
   return hipGetLastError();
 }
 
