@@ -296,13 +296,21 @@ __device__ __forceinline__ uint32_t end_dword(int64_t rem, int64_t bw) {
   return rem >= 0 && rem < bw ? (uint32_t)rem & ~3u : 0u;
 }
 
+// The pieces of lane j of a group, read from the block at blk (4-aligned;
+// rem = string bytes from its start). A piece that starts at or past the
+// string's end is masked whole by block_sum, so it is read from the block's
+// first piece instead (already on its way for the group's lane 0): the tail
+// of a string's last block is not fetched from memory.
 template <bool WIDE, int G>
 __device__ __forceinline__ void block_loads(Pieces<WIDE, G>& P, const uint8_t* blk, int j, uint32_t sh,
-                                            uint32_t eoff) {
+                                            uint32_t eoff, int64_t rem) {
   const uint8_t* gb = gaddr((uint64_t)(uintptr_t)blk);  // global loads, whatever the pointer's origin
+  constexpr int32_t BW = BLOCK * Tr<WIDE>::W;
+  const int32_t rc = rem > BW ? BW : (rem < 0 ? 0 : (int32_t)rem);  // string bytes in the block
 #pragma unroll
   for (int t = 0; t < Pieces<WIDE, G>::NL; ++t) {
-    const uint8_t* pa = gb + 16 * (t * G + j);
+    const int32_t o = 16 * (t * G + j);
+    const uint8_t* pa = gb + (o < rc ? o : 0);
     Q q = load16(pa);
     P.d[t][0] = q.d[0];
     P.d[t][1] = q.d[1];
@@ -466,7 +474,8 @@ __device__ typename Tr<WIDE>::Sum node_blocks(const BatchArgs& B, const uint64_t
   auto fill = [&](Pieces<WIDE, G>& P, bool& h, int64_t c0) {
     h = plain(c0);
     block_loads<WIDE, G>(P, h ? a4 + (c0 + g) * (int64_t)(BLOCK * W) : safe, j, sh,
-                         end_dword(len - (c0 + g) * (int64_t)(BLOCK * W), BLOCK * W));
+                         end_dword(len - (c0 + g) * (int64_t)(BLOCK * W), BLOCK * W),
+                         len - (c0 + g) * (int64_t)(BLOCK * W));
   };
   // two buffers used in turn, the loop unrolled twice so that neither is
   // ever copied (a copy costs a move per register and waits for the loads):
@@ -662,7 +671,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
       bs = block_guarded<WIDE, G>(blk, j, ssh, lk, act, sl, lo, hi);
     } else {
       Pieces<WIDE, G> P;
-      block_loads<WIDE, G>(P, blk, j, ssh, end_dword(act ? sl : -1, BW));
+      block_loads<WIDE, G>(P, blk, j, ssh, end_dword(act ? sl : -1, BW), act ? sl : -1);
       bs = block_sum<WIDE, G, true>(P, j, ssh, lk, act, sl);
     }
     group_sum<G>(bs);
@@ -724,7 +733,7 @@ __device__ void medium_strings(const BatchArgs& B, const uint64_t* lk, uint8_t* 
     auto issue = [&](Pieces<WIDE, G>& P, uint32_t t, Tk& k) {
       task(t, k.blk, k.sh, k.rem, k.own);
       k.have = t < tr && inside(k.blk, BW + 4, lo, hi);
-      block_loads<WIDE, G>(P, k.have ? k.blk : safe, j, k.sh, end_dword(k.rem, BW));
+      block_loads<WIDE, G>(P, k.have ? k.blk : safe, j, k.sh, end_dword(k.rem, BW), k.rem);
     };
     // the group's task of step st: sum, fold, field element to LDS
     auto compute = [&](const Pieces<WIDE, G>& P, const Tk& k, uint32_t st) {
