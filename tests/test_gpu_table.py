@@ -225,9 +225,10 @@ def test_table_all_hashes_equal(wide):
 def test_table_all_hashes_equal_long(wide):
     """As above with keys of 1 to 300 bytes (one block each), so that equal
     hash and length leave the bytes to decide: the queries copy keys whole
-    or with one byte changed at the first, last or a step boundary position
-    (bytes 0, 15, 16, 127, 128, 255 and the last), and lie at every offset
-    mod 16 from the keys."""
+    or with one byte changed at the first, the last or a position next to a
+    16-byte granule or 64-byte compare-round boundary (bytes 0, 15, 16, 63,
+    64, 127, 128, 191, 192, 255 and the last), and lie at every offset mod 16
+    from the keys."""
     import torch
 
     from paper_1609_09840_amd import pmp
@@ -241,7 +242,7 @@ def test_table_all_hashes_equal_long(wide):
     for q in range(900):
         src = kparts[int(rng.integers(0, len(kparts)))].copy()
         if q % 3 == 1:
-            cands = [p for p in (0, 15, 16, 127, 128, 255, src.size - 1) if p < src.size]
+            cands = [p for p in (0, 15, 16, 63, 64, 127, 128, 191, 192, 255, src.size - 1) if p < src.size]
             p = cands[int(rng.integers(0, len(cands)))]
             src[p] ^= np.uint8(1 + rng.integers(0, 255))
         elif q % 3 == 2:
