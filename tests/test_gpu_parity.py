@@ -257,6 +257,34 @@ def test_tiles_agree():
             plan.close()
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_last_block_ends(wide):
+    """Strings of 2 to 33 blocks (the medium path up to 32, then a long one)
+    whose last block holds r bytes, r next to every 16-byte piece boundary
+    that a lane of a group of 4, 8 or 16 lanes can own, at all four
+    alignments, for every compiled tile pair: the pieces of a last block
+    past the string's end are read from elsewhere and must not count."""
+    from paper_1609_09840_amd import pmp
+
+    bw = 128 * (8 if wide else 4)  # bytes per block
+    rs = sorted({r for p in range(0, bw, 16) for r in (p - 1, p, p + 1) if 0 <= r < bw} | {bw - 1})
+    rng = np.random.default_rng(131 + wide)
+    blocks = rng.integers(1, 33, size=len(rs))  # full blocks before the last one
+    lengths = np.array([int(b) * bw + r for b, r in zip(blocks, rs)], dtype=np.int64)
+    keys = U.keys_for(wide, 133)
+    for lead in range(4):
+        rg = W.from_lengths(lengths, 134 + lead, wide, lead=lead)
+        want = U.oracle_hash(rg, keys, 2)
+        for g32, g64 in TILE_PAIRS:
+            plan = pmp.Plan(0)
+            plan.set_tile(False, g32)
+            plan.set_tile(True, g64)
+            say(f"case last-block ends wide={wide} lead={lead} tiles ({g32}, {g64}) count={rg.count}")
+            got = U.gpu_hash(rg, keys, 2, plan=plan)
+            assert U.first_mismatch(got, want) is None, (lead, g32, g64, U.first_mismatch(got, want))
+            plan.close()
+
+
 @pytest.mark.parametrize("shares", [1, 4])
 def test_split_by_count(shares):
     """Shares cut by string count (PMP_ALPHA_BY_COUNT, no offset search):
