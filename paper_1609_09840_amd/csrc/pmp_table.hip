@@ -144,7 +144,7 @@ constexpr int STEP = 64;
 // (such a chunk lies in the string's memory page) and any other one from the
 // first chunk's, so that no load is conditional; then the chunks are shifted
 // down by the string's offset in its first chunk: whole dwords with two
-// rounds of selects, then bytes with alignbyte.
+// rounds of byte permutes, then bytes with alignbyte.
 __device__ __forceinline__ void load_step(const uint8_t* p, int64_t o, int64_t r, uint32_t* x) {
   constexpr int NC = STEP / 16 + 1;  // chunks that can hold the bytes
   const uint64_t a = (uint64_t)(uintptr_t)p + (uint64_t)o;
@@ -194,9 +194,9 @@ __device__ __forceinline__ bool bytes_equal(const uint8_t* a, const uint8_t* b, 
   return true;
 }
 
-__global__ void __launch_bounds__(256) tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf,
-                          uint32_t wide, uint64_t m, const int64_t* start, const pmp_table_entry* entries,
-                          int64_t* result) {
+__global__ void __launch_bounds__(256)
+    tab_probe(const uint8_t* qbuf, const int64_t* qoff, int64_t nq, const void* qh, const uint8_t* kbuf, uint32_t wide,
+              uint64_t m, const int64_t* start, const pmp_table_entry* entries, int64_t* result) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q0 = qoff[q], len = qoff[q + 1] - q0;
     const uint64_t hq = hash_at(qh, wide, q);
